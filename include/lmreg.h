@@ -1,0 +1,192 @@
+/*
+ * lmreg — one factored Levenberg–Marquardt (LM) step of dense 3D image
+ * registration on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Factored Levenberg–Marquardt for Diffeomorphic Image
+ * Registration" (arXiv 2603.19371).  One LM attempt on a pair (F, M) with
+ * displacement field u:
+ *   1. closed-form damped rank-1 step  du = -r g / (|g|^2 + lambda)
+ *      (Sec. 2.2, eq. tile1; derivation in App. A), with g the smoothed
+ *      gradient of the accepted field and r = 1 - LNCC its residual
+ *      (Sec. 2.2, squared-loss form of LNCC);
+ *   2. compositive integration  u~ = eps du + u o (Id + eps du)
+ *      (Sec. 2.1, eq. compositive);
+ *   3. loss of the candidate  L = -mean_x cc(x), cc the windowed squared
+ *      correlation of F and M o (Id + u~) (Sec. 1, eq. 1; Sec. 2.2);
+ *   4. damping rule (Sec. 2.2, eq. lambda-update) and rejection test
+ *      (Sec. 2.2, eq. delta-loss; Sec. 3.4, eq. rejection), decided on the
+ *      device from an FP64 reduction of the loss;
+ *   5. if accepted, the analytic gradient of the loss with respect to u,
+ *      Gaussian-smoothed (Eulerian descent, Sec. 2.1), for the next attempt.
+ *
+ * Conventions for every call:
+ *   - Volumes are dense [nz][ny][nx] arrays with x fastest.  Images are FP32
+ *     or BF16 (lmr_dtype); fields are FP32 [3][nz][ny][nx] where component
+ *     0/1/2 is the displacement along x/y/z in voxel units.
+ *   - Pointers named as device pointers are caller-owned device memory of the
+ *     current HIP device; the library never frees or retains them beyond the
+ *     call (a context keeps no pointer to caller images between calls).
+ *   - Work is enqueued on the stream the context (or the call) is bound to and
+ *     returns without synchronising, except where a call says it synchronises.
+ *   - Every call returns an lmr_status.  Invalid arguments give LMR_EINVAL and
+ *     enqueue nothing.  A failing HIP runtime call gives LMR_EHIP (the HIP
+ *     error string is kept, see lmr_last_error).  Asynchronous kernel faults
+ *     surface at the next synchronising call.  No exception or abort crosses
+ *     this interface.
+ *   - A context is bound to one stream and is not re-entrant; separate
+ *     contexts may be used concurrently from different threads.
+ */
+#ifndef LMREG_H
+#define LMREG_H
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LMR_VERSION_MAJOR 0
+#define LMR_VERSION_MINOR 1
+
+typedef enum {
+  LMR_OK = 0,
+  LMR_EINVAL = 1,   /* invalid argument (shape, pointer, parameter) */
+  LMR_ENOMEM = 2,   /* device allocation failed */
+  LMR_EHIP = 3,     /* a HIP runtime call failed */
+  LMR_ESTATE = 4,   /* call out of order (e.g. lmr_step before lmr_begin) */
+  LMR_ESTALLED = 5  /* the pair is frozen (see lmr_params.max_retries) */
+} lmr_status;
+
+typedef enum { LMR_F32 = 0, LMR_BF16 = 1 } lmr_dtype;
+
+/* Accumulator of the LNCC box sums.  LMR_ACC_F64: exact FP32 products summed
+ * in FP64 (default: on gfx950 an FP64 add issues at the rate of an unpacked
+ * FP32 add).  LMR_ACC_F32C: FP32 hi/lo pairs with error-free TwoSum/TwoProd
+ * (compensated FP32). */
+typedef enum { LMR_ACC_F64 = 0, LMR_ACC_F32C = 1 } lmr_accum;
+
+/* Hyper-parameters of one registration.  The paper's own setting
+ * (Sec. 3: lambda0 = 0.006, mu+ = 1.5, mu- = 0.975, no rejection) and the
+ * synthetic-phantom setting (lambda x2 / x0.5, rejection with tau = 0) are
+ * both expressible; lmr_default_params fills the latter. */
+typedef struct {
+  int    window;       /* LNCC box side w: odd, 3..9 */
+  double grad_sigma;   /* Gaussian sigma (voxels) on the gradient, 0..2; 0 = off.
+                          Taps k in [-R, R], R = ceil(3 sigma), zero padding */
+  double cc_eps;       /* guard added to the LNCC denominator (>= 0) */
+  double step_eps;     /* eps of eq. compositive (> 0) */
+  int    compositive;  /* 1: eq. compositive; 0: additive u + eps du */
+  int    accum;        /* lmr_accum of the box sums */
+  double lambda_inc;   /* mu+ > 1 */
+  double lambda_dec;   /* 0 < mu- < 1 */
+  double lambda_min;   /* lower clamp of lambda (> 0) */
+  double lambda_max;   /* cap of lambda (Sec. 3.4); may be +inf */
+  double tau;          /* rejection tolerance (eq. rejection); < 0 disables */
+  int    max_retries;  /* consecutive rejections at lambda_max that freeze the pair */
+} lmr_params;
+
+/* The whole optimizer state of one pair: the scalar damping and the loss
+ * history that the rejection test needs (Sec. 2.2). */
+typedef struct {
+  double    lambda;     /* damping of the next attempt */
+  double    loss;       /* L of the accepted field (L^(t-1) for the next candidate) */
+  double    loss_prev;  /* L of the field accepted before it (L^(t-2)) */
+  double    cand_loss;  /* L of the last candidate */
+  int32_t   n_hist;     /* accepted losses recorded (1 after lmr_begin) */
+  int32_t   retries;    /* consecutive rejections */
+  int32_t   accepted;   /* decision of the last attempt (1 accept, 0 reject) */
+  int32_t   stalled;    /* 1 once the pair is frozen */
+  int64_t   attempts;   /* attempts evaluated since lmr_begin */
+} lmr_pair_state;
+
+typedef struct lmr_ctx lmr_ctx;
+
+/* ------------------------------------------------------------------------ */
+const char* lmr_strerror(lmr_status s);
+/* Text of the last HIP error seen by this thread (empty if none). */
+const char* lmr_last_error(void);
+void lmr_default_params(lmr_params* p);
+
+/* Creates a context for volumes of nz*ny*nx voxels with images of type img,
+ * bound to `stream` (0 = the null stream).  Allocates the whole workspace
+ * (about 80 bytes per voxel: field ping-pong, smoothed gradient, raw
+ * gradient, four LNCC adjoint maps, warped image, reduction partials and the
+ * device pair state); no later call allocates.  Sizes: each dimension >= 1,
+ * nz*ny*nx < 2^31.  Errors: LMR_EINVAL (shape/params), LMR_ENOMEM. */
+lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
+                      const lmr_params* p, hipStream_t stream);
+void lmr_destroy(lmr_ctx* ctx);
+
+/* Starts a registration from `field` (device, [3][nz][ny][nx] FP32; NULL =
+ * identity u = 0) with damping lambda0 > 0: evaluates L(u) and the smoothed
+ * gradient of u.  fixed/moving: device images of the context's type. */
+lmr_status lmr_begin(lmr_ctx* ctx, const void* fixed, const void* moving,
+                     const float* field, double lambda0);
+
+/* Enqueues n_attempts LM attempts (steps 1-5 above).  Each attempt reads the
+ * accepted field, its smoothed gradient and (lambda, r) from device memory
+ * and leaves the decision there; nothing returns to the host, so the calls
+ * may be captured in a HIP graph.  A frozen pair skips its work.
+ * Errors: LMR_ESTATE before lmr_begin. */
+lmr_status lmr_step(lmr_ctx* ctx, const void* fixed, const void* moving,
+                    int n_attempts);
+
+/* As lmr_step, with the accept/reject decision of attempt i forced to
+ * decisions[i] (host array; 1 accept, 0 reject, -1 automatic).  Lambda and
+ * the loss history follow the forced decision exactly as they would follow
+ * an automatic one.  Used to replay a recorded trajectory. */
+lmr_status lmr_step_forced(lmr_ctx* ctx, const void* fixed, const void* moving,
+                           const int* decisions, int n);
+
+/* Copies the accepted field into field_out (device, [3][nz][ny][nx]). */
+lmr_status lmr_get_field(lmr_ctx* ctx, float* field_out);
+/* Copies the smoothed gradient of the accepted field into g_out (device). */
+lmr_status lmr_get_grad(lmr_ctx* ctx, float* g_out);
+/* Synchronises the context's stream and returns the pair state. */
+lmr_status lmr_get_state(lmr_ctx* ctx, lmr_pair_state* out);
+/* Overwrites the device pair state with `in` (host struct): lambda, the loss
+ * history, counters and flags.  With lmr_begin on a saved field this resumes
+ * a registration from a checkpoint (lmr_get_field + lmr_get_state); the
+ * resumed attempts are bitwise identical to the uninterrupted ones when `in`
+ * holds the saved state.  Requires lambda > 0 and n_hist >= 1.  Asynchronous
+ * (the struct is copied before the call returns). */
+lmr_status lmr_set_state(lmr_ctx* ctx, const lmr_pair_state* in);
+
+/* Test hook: loss and gradients of an arbitrary field u (device) without
+ * touching the pair state.  loss_out (host) receives L = -mean cc; g_raw and
+ * g_smooth (device, [3][nz][ny][nx], either may be NULL) receive N dL/du and
+ * its Gaussian-smoothed version; cc_map (device [nz][ny][nx], may be NULL)
+ * receives cc(x).  Synchronises. */
+lmr_status lmr_loss_grad(lmr_ctx* ctx, const void* fixed, const void* moving,
+                         const float* u, double* loss_out, float* g_raw,
+                         float* g_smooth, float* cc_map);
+
+/* Test hook: steps 1-2 alone.  u_out = eps du + u o (Id + eps du) with
+ * du = -r g / (|g|^2 + lambda) (device arrays, [3][nz][ny][nx]). */
+lmr_status lmr_update(lmr_ctx* ctx, const float* u, const float* g_smooth,
+                      double r, double lambda, float* u_out);
+
+/* Gaussian smoothing of a field (step 5 alone): out = G_sigma * g with the
+ * context's grad_sigma, taps k in [-R, R], R = ceil(3 sigma), zero padding
+ * (Eulerian descent, Sec. 2.1).  g and out: device [3][nz][ny][nx], distinct. */
+lmr_status lmr_smooth(lmr_ctx* ctx, const float* g, float* out);
+
+/* Test hook: step 4 alone.  Runs the device decision once on the state
+ * `in` with candidate loss cand_loss and forced decision `force` (-1
+ * automatic, 0 reject, 1 accept), and returns the resulting state in `out`
+ * (host structs).  Uses a private device state: the context's pair state is
+ * untouched.  Synchronises. */
+lmr_status lmr_decide_probe(lmr_ctx* ctx, const lmr_pair_state* in,
+                            double cand_loss, int force, lmr_pair_state* out);
+
+/* Trilinear warp Mw(x) = M(x + u(x)), zero outside the volume; dMw (may be
+ * NULL) receives d/dp M at x + u(x) as [3][nz][ny][nx].  Device arrays. */
+lmr_status lmr_warp(const void* moving, lmr_dtype img, const float* u,
+                    int nz, int ny, int nx, float* Mw, float* dMw,
+                    hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LMREG_H */

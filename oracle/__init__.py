@@ -73,6 +73,8 @@ def lib():
             "orc_loss_grad": (d, [_D, _D, _D, i, i, i, i, d, _D]),
             "orc_grad_at": (None, [_D, _D, _D, i, i, i, i, d, i, i, i, _D]),
             "orc_gauss": (None, [_D, i, i, i, i, d, _D]),
+            "orc_cc_at": (d, [_D, _D, _D, i, i, i, i, d, i, i, i]),
+            "orc_gauss_at": (None, [_D, i, i, i, i, d, i, i, i, _D]),
             "orc_gauss_radius": (i, [d]),
             "orc_closed_form": (None, [_D, i, i, i, d, d, _D]),
             "orc_explicit_solve": (None, [_D, d, d, _D]),
@@ -222,6 +224,12 @@ def grad_at(F, M, u, w, eps, x, y, z):
     return g
 
 
+def cc_at(F, M, u, w, eps, x, y, z):
+    F, M, u = _f64(F), _f64(M), _f64(u)
+    return lib().orc_cc_at(_p(F), _p(M), _p(u), *F.shape, int(w), float(eps),
+                           int(x), int(y), int(z))
+
+
 # ---------------------------------------------------------------- O4..O6
 def gauss_radius(sigma):
     return int(lib().orc_gauss_radius(float(sigma)))
@@ -233,6 +241,15 @@ def gauss(g, sigma):
     shp = g.shape[-3:]
     out = np.empty_like(g)
     lib().orc_gauss(_p(g), nc, *shp, float(sigma), _p(out))
+    return out
+
+
+def gauss_at(g, sigma, x, y, z):
+    g = _f64(g)
+    nc = 1 if g.ndim == 3 else g.shape[0]
+    out = np.zeros(nc)
+    lib().orc_gauss_at(_p(g), nc, *g.shape[-3:], float(sigma), int(x), int(y),
+                       int(z), _p(out))
     return out
 
 

@@ -330,6 +330,30 @@ void orc_grad_at(const double* F, const double* M, const double* u, int nz,
   free(in);
 }
 
+double orc_cc_at(const double* F, const double* M, const double* u, int nz,
+                 int ny, int nx, int w, double eps, int x, int y, int z) {
+  long N = (long)nz * ny * nx;
+  int h = w / 2;
+  double st[5] = {0, 0, 0, 0, 0};
+  for (int dz = -h; dz <= h; dz++)
+    for (int dy = -h; dy <= h; dy++)
+      for (int dx = -h; dx <= h; dx++) {
+        int zz = z + dz, yy = y + dy, xx = x + dx;
+        if (zz < 0 || zz >= nz || yy < 0 || yy >= ny || xx < 0 || xx >= nx)
+          continue;
+        long i = IDX(zz, yy, xx);
+        double f = F[i];
+        double m = orc_sample(M, nz, ny, nx, xx + u[i], yy + u[N + i],
+                              zz + u[2 * N + i], NULL);
+        st[0] += f;
+        st[1] += m;
+        st[2] += f * f;
+        st[3] += m * m;
+        st[4] += f * m;
+      }
+  return local_from_sums(st, w, eps).cc;
+}
+
 /* ------------------------------------------------------------------------ */
 /* O4  Gaussian smoothing of the gradient (Eulerian descent, Sec. 2.1; the   */
 /*     paper defers the filter to FireANTs).  Reading: taps k in [-R, R],    */
@@ -374,6 +398,30 @@ void orc_gauss(const double* g, int nc, int nz, int ny, int nx, double sigma,
         }
   }
   free(wt);
+}
+
+void orc_gauss_at(const double* g, int nc, int nz, int ny, int nx, double sigma,
+                  int x, int y, int z, double* out) {
+  long N = (long)nz * ny * nx;
+  int R = orc_gauss_radius(sigma);
+  double wt[64], tot = 0.0;
+  for (int k = -R; k <= R; k++) {
+    wt[k + R] = (R == 0) ? 1.0 : exp(-(double)k * k / (2.0 * sigma * sigma));
+    tot += wt[k + R];
+  }
+  for (int k = 0; k <= 2 * R; k++) wt[k] /= tot;
+  for (int c = 0; c < nc; c++) {
+    double s = 0.0;
+    for (int dz = -R; dz <= R; dz++)
+      for (int dy = -R; dy <= R; dy++)
+        for (int dx = -R; dx <= R; dx++) {
+          int zz = z + dz, yy = y + dy, xx = x + dx;
+          if (zz < 0 || zz >= nz || yy < 0 || yy >= ny || xx < 0 || xx >= nx)
+            continue;
+          s += wt[dz + R] * wt[dy + R] * wt[dx + R] * g[c * N + IDX(zz, yy, xx)];
+        }
+    out[c] = s;
+  }
 }
 
 /* ------------------------------------------------------------------------ */

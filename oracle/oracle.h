@@ -78,11 +78,18 @@ void orc_grad_at(const double* F, const double* M, const double* u,
                  int nz, int ny, int nx, int w, double eps,
                  int x, int y, int z, double g[3]);
 
+/* O2 at one voxel: cc(x) of (F, M o (Id + u)), warping only the window. */
+double orc_cc_at(const double* F, const double* M, const double* u, int nz,
+                 int ny, int nx, int w, double eps, int x, int y, int z);
+
 /* O4: 3D Gaussian of nc channels, taps k in [-R,R], R = ceil(3 sigma),
  * zero outside, weights normalised over the full tap range. */
 void orc_gauss(const double* g, int nc, int nz, int ny, int nx, double sigma,
                double* out);
 int  orc_gauss_radius(double sigma);
+/* O4 at one voxel, nc channels. */
+void orc_gauss_at(const double* g, int nc, int nz, int ny, int nx, double sigma,
+                  int x, int y, int z, double* out);
 
 /* O5: closed-form damped rank-1 step (eq. tile1). */
 void orc_closed_form(const double* gs, int nz, int ny, int nx, double r,

@@ -1,0 +1,264 @@
+"""ctypes binding of liblmreg (include/lmreg.h).
+
+Argument marshalling only: every step of the registration runs in the HIP
+kernels of liblmreg.so.  torch provides device memory and streams.  Before a
+call reaches the library, the binding checks on the host that every tensor is
+a contiguous CUDA tensor of the dtype and shape the call expects, so that no
+kernel is launched on a buffer smaller than its grid assumes.
+
+There is no fallback: if liblmreg.so is missing or fails to load, importing
+this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblmreg.so")
+
+LMR_F32, LMR_BF16 = 0, 1
+LMR_ACC_F64, LMR_ACC_F32C = 0, 1
+_STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory",
+           3: "HIP runtime error", 4: "call out of order", 5: "pair is frozen"}
+
+
+class LmrError(RuntimeError):
+    pass
+
+
+class Params(C.Structure):
+    """Mirror of lmr_params."""
+    _fields_ = [("window", C.c_int), ("grad_sigma", C.c_double),
+                ("cc_eps", C.c_double), ("step_eps", C.c_double),
+                ("compositive", C.c_int), ("accum", C.c_int),
+                ("lambda_inc", C.c_double), ("lambda_dec", C.c_double),
+                ("lambda_min", C.c_double), ("lambda_max", C.c_double),
+                ("tau", C.c_double), ("max_retries", C.c_int)]
+
+    @staticmethod
+    def make(**kw) -> "Params":
+        p = Params()
+        lib().lmr_default_params(C.byref(p))
+        for k, v in kw.items():
+            if not hasattr(p, k):
+                raise KeyError(k)
+            setattr(p, k, v)
+        return p
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class PairState(C.Structure):
+    """Mirror of lmr_pair_state."""
+    _fields_ = [("lambda_", C.c_double), ("loss", C.c_double),
+                ("loss_prev", C.c_double), ("cand_loss", C.c_double),
+                ("n_hist", C.c_int32), ("retries", C.c_int32),
+                ("accepted", C.c_int32), ("stalled", C.c_int32),
+                ("attempts", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+_V, _I, _D, _LL = C.c_void_p, C.c_int, C.c_double, C.c_longlong
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LmrError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2603_19371_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "lmr_strerror": (C.c_char_p, [_I]),
+            "lmr_last_error": (C.c_char_p, []),
+            "lmr_default_params": (None, [C.POINTER(Params)]),
+            "lmr_create": (_I, [C.POINTER(_V), _I, _I, _I, _I, C.POINTER(Params), _V]),
+            "lmr_destroy": (None, [_V]),
+            "lmr_begin": (_I, [_V, _V, _V, _V, _D]),
+            "lmr_step": (_I, [_V, _V, _V, _I]),
+            "lmr_step_forced": (_I, [_V, _V, _V, C.POINTER(_I), _I]),
+            "lmr_get_field": (_I, [_V, _V]),
+            "lmr_get_grad": (_I, [_V, _V]),
+            "lmr_get_state": (_I, [_V, C.POINTER(PairState)]),
+            "lmr_loss_grad": (_I, [_V, _V, _V, _V, C.POINTER(_D), _V, _V, _V]),
+            "lmr_update": (_I, [_V, _V, _V, _D, _D, _V]),
+            "lmr_warp": (_I, [_V, _I, _V, _I, _I, _I, _V, _V, _V]),
+            "lmr_decide_probe": (_I, [_V, C.POINTER(PairState), _D, _I,
+                                      C.POINTER(PairState)]),
+            "lmr_smooth": (_I, [_V, _V, _V]),
+            "lmr_set_state": (_I, [_V, C.POINTER(PairState)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names this binding requires the library to export."""
+    lib()
+    return ["lmr_strerror", "lmr_last_error", "lmr_default_params", "lmr_create",
+            "lmr_destroy", "lmr_begin", "lmr_step", "lmr_step_forced",
+            "lmr_get_field", "lmr_get_grad", "lmr_get_state", "lmr_loss_grad",
+            "lmr_update", "lmr_warp", "lmr_decide_probe", "lmr_smooth",
+            "lmr_set_state"]
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        detail = lib().lmr_last_error().decode()
+        raise LmrError(f"{what}: {_STATUS.get(status, status)}"
+                       + (f" ({detail})" if detail else ""))
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _img_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return LMR_F32
+    if t.dtype == torch.bfloat16:
+        return LMR_BF16
+    raise LmrError(f"image dtype must be float32 or bfloat16, got {t.dtype}")
+
+
+def _dev(t: torch.Tensor, shape, dtype, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise LmrError(f"{name} must be a CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise LmrError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.dtype != dtype:
+        raise LmrError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise LmrError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+class Context:
+    """One registration pair on one stream (lmr_ctx)."""
+
+    def __init__(self, shape, img_dtype=torch.float32, params: Params | None = None,
+                 stream=None, **kw):
+        self.shape = tuple(int(s) for s in shape)
+        self.img_dtype = img_dtype
+        self.params = params if params is not None else Params.make(**kw)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._h = _V()
+        code = LMR_BF16 if img_dtype == torch.bfloat16 else LMR_F32
+        _check(lib().lmr_create(C.byref(self._h), *self.shape, code,
+                                C.byref(self.params), _stream_handle(self.stream)),
+               "lmr_create")
+
+    def close(self):
+        if self._h:
+            lib().lmr_destroy(self._h)
+            self._h = _V()
+
+    __del__ = close
+
+    def _imgs(self, F, M):
+        return (_dev(F, self.shape, self.img_dtype, "fixed"),
+                _dev(M, self.shape, self.img_dtype, "moving"))
+
+    def _field(self, u, name="field"):
+        return _dev(u, (3,) + self.shape, torch.float32, name)
+
+    def begin(self, F, M, field=None, lambda0=1.0):
+        f, m = self._imgs(F, M)
+        u = self._field(field) if field is not None else None
+        _check(lib().lmr_begin(self._h, f, m, u, float(lambda0)), "lmr_begin")
+        return self
+
+    def step(self, F, M, n=1):
+        f, m = self._imgs(F, M)
+        _check(lib().lmr_step(self._h, f, m, int(n)), "lmr_step")
+
+    def step_forced(self, F, M, decisions):
+        f, m = self._imgs(F, M)
+        arr = (C.c_int * len(decisions))(*[int(d) for d in decisions])
+        _check(lib().lmr_step_forced(self._h, f, m, arr, len(decisions)),
+               "lmr_step_forced")
+
+    def field(self, out=None):
+        out = out if out is not None else torch.empty((3,) + self.shape,
+                                                      device="cuda")
+        _check(lib().lmr_get_field(self._h, self._field(out, "out")), "lmr_get_field")
+        return out
+
+    def grad(self, out=None):
+        out = out if out is not None else torch.empty((3,) + self.shape,
+                                                      device="cuda")
+        _check(lib().lmr_get_grad(self._h, self._field(out, "out")), "lmr_get_grad")
+        return out
+
+    def state(self) -> dict:
+        s = PairState()
+        _check(lib().lmr_get_state(self._h, C.byref(s)), "lmr_get_state")
+        return s.as_dict()
+
+    def set_state(self, state: dict):
+        s = PairState(**{k: state.get(k, 0) for k, _ in PairState._fields_})
+        _check(lib().lmr_set_state(self._h, C.byref(s)), "lmr_set_state")
+
+    def loss_grad(self, F, M, u, raw=True, smooth=True, cc=False):
+        f, m = self._imgs(F, M)
+        up = self._field(u, "u")
+        gr = torch.empty((3,) + self.shape, device="cuda") if raw else None
+        gs = torch.empty((3,) + self.shape, device="cuda") if smooth else None
+        cm = torch.empty(self.shape, device="cuda") if cc else None
+        L = C.c_double()
+        _check(lib().lmr_loss_grad(self._h, f, m, up, C.byref(L),
+                                   gr.data_ptr() if raw else None,
+                                   gs.data_ptr() if smooth else None,
+                                   cm.data_ptr() if cc else None), "lmr_loss_grad")
+        return L.value, gr, gs, cm
+
+    def smooth(self, g, out=None):
+        out = out if out is not None else torch.empty((3,) + self.shape,
+                                                      device="cuda")
+        if out.data_ptr() == g.data_ptr():
+            raise LmrError("smooth: g and out must be distinct")
+        _check(lib().lmr_smooth(self._h, self._field(g, "g"),
+                                self._field(out, "out")), "lmr_smooth")
+        return out
+
+    def decide_probe(self, state: dict, cand_loss: float, force: int = -1) -> dict:
+        sin = PairState(**{k: state.get(k, 0) for k, _ in PairState._fields_})
+        sout = PairState()
+        _check(lib().lmr_decide_probe(self._h, C.byref(sin), float(cand_loss),
+                                      int(force), C.byref(sout)), "lmr_decide_probe")
+        return sout.as_dict()
+
+    def update(self, u, g_smooth, r, lam, out=None):
+        out = out if out is not None else torch.empty((3,) + self.shape,
+                                                      device="cuda")
+        _check(lib().lmr_update(self._h, self._field(u, "u"),
+                                self._field(g_smooth, "g_smooth"), float(r),
+                                float(lam), self._field(out, "out")), "lmr_update")
+        return out
+
+
+def warp(M: torch.Tensor, u: torch.Tensor, with_grad=False, stream=None):
+    shape = tuple(M.shape)
+    if len(shape) != 3:
+        raise LmrError("moving must be [nz][ny][nx]")
+    m = _dev(M, shape, M.dtype, "moving")
+    up = _dev(u, (3,) + shape, torch.float32, "u")
+    Mw = torch.empty(shape, device=M.device)
+    dMw = torch.empty((3,) + shape, device=M.device) if with_grad else None
+    _check(lib().lmr_warp(m, _img_code(M), up, *shape, Mw.data_ptr(),
+                          dMw.data_ptr() if with_grad else None,
+                          _stream_handle(stream)), "lmr_warp")
+    return (Mw, dMw) if with_grad else Mw

@@ -1,0 +1,356 @@
+// C-ABI of liblmreg: contexts, workspace and the step sequence of one LM
+// attempt (include/lmreg.h documents every entry point).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "lmr_internal.h"
+
+using namespace lmr;
+
+struct lmr_ctx {
+  Geom g;
+  lmr_dtype img;
+  lmr_params p;
+  DecideParams dp;
+  hipStream_t stream;
+  void* arena;
+  float* U[2];
+  float* G;
+  float* graw;
+  float* maps;
+  float* Mw;
+  double* partials;
+  int nparts;
+  DevState* st;
+  double* probe;
+  DevState* st_probe;
+  double* part_probe;
+  bool begun;
+};
+
+namespace {
+
+thread_local char g_err[256] = "";
+
+lmr_status hip_fail(hipError_t e) {
+  snprintf(g_err, sizeof g_err, "%s", hipGetErrorString(e));
+  return LMR_EHIP;
+}
+
+#define LMR_HIP(expr)                         \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+
+bool params_ok(const lmr_params* p) {
+  if (!p) return false;
+  if (p->window < 3 || p->window > 9 || (p->window % 2) == 0) return false;
+  if (!(p->grad_sigma >= 0.0 && p->grad_sigma <= 2.0)) return false;
+  if (!(p->cc_eps >= 0.0)) return false;
+  if (!(p->step_eps > 0.0)) return false;
+  if (p->accum != LMR_ACC_F64) return false;
+  if (!(p->lambda_inc > 1.0) || !(p->lambda_dec > 0.0 && p->lambda_dec < 1.0)) return false;
+  if (!(p->lambda_min > 0.0) || !(p->lambda_max >= p->lambda_min)) return false;
+  if (p->max_retries < 1) return false;
+  return true;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// One attempt: P1 update, P2 forward, P3 decide, P4 backward, P5 smooth.
+lmr_status enqueue_attempt(lmr_ctx* c, const void* F, const void* M, int force) {
+  hipStream_t s = c->stream;
+  LMR_HIP(launch_update(M, c->img, c->g, c->p, c->st, c->G, c->U[0], c->U[1], nullptr,
+                        nullptr, 0.0, 0.0, c->Mw, s));
+  LMR_HIP(launch_fwd(F, c->img, c->Mw, c->g, c->p, c->st, c->maps, c->partials,
+                     nullptr, s));
+  LMR_HIP(launch_decide(c->st, c->partials, c->nparts, c->g.N, c->dp, 0, force, 0.0,
+                        nullptr, s));
+  LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, c->st, c->U[0], c->U[1],
+                     nullptr, c->graw, s));
+  LMR_HIP(launch_smooth(c->graw, c->g, c->p, c->st, c->G, s));
+  return LMR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lmr_strerror(lmr_status s) {
+  switch (s) {
+    case LMR_OK: return "ok";
+    case LMR_EINVAL: return "invalid argument";
+    case LMR_ENOMEM: return "out of device memory";
+    case LMR_EHIP: return "HIP runtime error";
+    case LMR_ESTATE: return "call out of order";
+    case LMR_ESTALLED: return "pair is frozen";
+  }
+  return "unknown status";
+}
+
+const char* lmr_last_error(void) { return g_err; }
+
+void lmr_default_params(lmr_params* p) {
+  if (!p) return;
+  p->window = 5;
+  p->grad_sigma = 1.0;
+  p->cc_eps = 1e-5;
+  p->step_eps = 1.0;
+  p->compositive = 1;
+  p->accum = LMR_ACC_F64;
+  p->lambda_inc = 2.0;
+  p->lambda_dec = 0.5;
+  p->lambda_min = 1e-12;
+  p->lambda_max = 1e6;
+  p->tau = 0.0;
+  p->max_retries = 10;
+}
+
+lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
+                      const lmr_params* p, hipStream_t stream) {
+  if (!out) return LMR_EINVAL;
+  *out = nullptr;
+  if (nz < 1 || ny < 1 || nx < 1 || nz > 65535) return LMR_EINVAL;
+  long long N = (long long)nz * ny * nx;
+  if (N >= (1LL << 31)) return LMR_EINVAL;
+  if (img != LMR_F32 && img != LMR_BF16) return LMR_EINVAL;
+  if (!params_ok(p)) return LMR_EINVAL;
+
+  lmr_ctx* c = new (std::nothrow) lmr_ctx();
+  if (!c) return LMR_ENOMEM;
+  c->g = Geom{nz, ny, nx, N};
+  c->img = img;
+  c->p = *p;
+  c->dp = DecideParams{p->lambda_inc, p->lambda_dec, p->lambda_min, p->lambda_max,
+                       p->tau, p->max_retries};
+  c->stream = stream;
+  c->nparts = fwd_num_blocks(c->g, p->window);
+
+  const size_t f3 = align256(sizeof(float) * 3 * N);
+  const size_t sizes[] = {f3,
+                          f3,
+                          f3,
+                          f3,
+                          align256(sizeof(float) * 4 * N),
+                          align256(sizeof(float) * N),
+                          align256(sizeof(double) * c->nparts),
+                          align256(sizeof(DevState)),
+                          align256(sizeof(double)),
+                          align256(sizeof(DevState)),
+                          align256(sizeof(double))};
+  size_t total = 0;
+  for (size_t s : sizes) total += s;
+  hipError_t e = hipMalloc(&c->arena, total);
+  if (e != hipSuccess) {
+    snprintf(g_err, sizeof g_err, "%s", hipGetErrorString(e));
+    delete c;
+    return LMR_ENOMEM;
+  }
+  char* q = static_cast<char*>(c->arena);
+  c->U[0] = reinterpret_cast<float*>(q); q += sizes[0];
+  c->U[1] = reinterpret_cast<float*>(q); q += sizes[1];
+  c->G = reinterpret_cast<float*>(q); q += sizes[2];
+  c->graw = reinterpret_cast<float*>(q); q += sizes[3];
+  c->maps = reinterpret_cast<float*>(q); q += sizes[4];
+  c->Mw = reinterpret_cast<float*>(q); q += sizes[5];
+  c->partials = reinterpret_cast<double*>(q); q += sizes[6];
+  c->st = reinterpret_cast<DevState*>(q); q += sizes[7];
+  c->probe = reinterpret_cast<double*>(q); q += sizes[8];
+  c->st_probe = reinterpret_cast<DevState*>(q); q += sizes[9];
+  c->part_probe = reinterpret_cast<double*>(q);
+  c->begun = false;
+  *out = c;
+  return LMR_OK;
+}
+
+void lmr_destroy(lmr_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(c->arena);
+  delete c;
+}
+
+lmr_status lmr_begin(lmr_ctx* c, const void* F, const void* M, const float* field,
+                     double lambda0) {
+  if (!c || !F || !M || !(lambda0 > 0.0)) return LMR_EINVAL;
+  hipStream_t s = c->stream;
+  const size_t bytes = sizeof(float) * 3 * c->g.N;
+  if (field)
+    LMR_HIP(hipMemcpyAsync(c->U[0], field, bytes, hipMemcpyDeviceToDevice, s));
+  else
+    LMR_HIP(launch_fill(c->U[0], 3 * c->g.N, 0.0f, s));
+  LMR_HIP(launch_warp(M, c->img, c->U[0], c->g, c->Mw, nullptr, s));
+  LMR_HIP(launch_fwd(F, c->img, c->Mw, c->g, c->p, nullptr, c->maps, c->partials,
+                     nullptr, s));
+  LMR_HIP(launch_decide(c->st, c->partials, c->nparts, c->g.N, c->dp, 1, -1, lambda0,
+                        nullptr, s));
+  LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, nullptr, nullptr,
+                     nullptr, c->U[0], c->graw, s));
+  LMR_HIP(launch_smooth(c->graw, c->g, c->p, nullptr, c->G, s));
+  c->begun = true;
+  return LMR_OK;
+}
+
+lmr_status lmr_step(lmr_ctx* c, const void* F, const void* M, int n) {
+  if (!c || !F || !M || n < 0) return LMR_EINVAL;
+  if (!c->begun) return LMR_ESTATE;
+  for (int i = 0; i < n; ++i) {
+    lmr_status r = enqueue_attempt(c, F, M, -1);
+    if (r != LMR_OK) return r;
+  }
+  return LMR_OK;
+}
+
+lmr_status lmr_step_forced(lmr_ctx* c, const void* F, const void* M,
+                           const int* decisions, int n) {
+  if (!c || !F || !M || n < 0 || (n > 0 && !decisions)) return LMR_EINVAL;
+  if (!c->begun) return LMR_ESTATE;
+  for (int i = 0; i < n; ++i) {
+    int d = decisions[i] < 0 ? -1 : (decisions[i] ? 1 : 0);
+    lmr_status r = enqueue_attempt(c, F, M, d);
+    if (r != LMR_OK) return r;
+  }
+  return LMR_OK;
+}
+
+lmr_status lmr_get_field(lmr_ctx* c, float* out) {
+  if (!c || !out) return LMR_EINVAL;
+  if (!c->begun) return LMR_ESTATE;
+  LMR_HIP(launch_copy_cur(c->st, c->U[0], c->U[1], out, 3 * c->g.N, c->stream));
+  return LMR_OK;
+}
+
+lmr_status lmr_get_grad(lmr_ctx* c, float* out) {
+  if (!c || !out) return LMR_EINVAL;
+  if (!c->begun) return LMR_ESTATE;
+  LMR_HIP(hipMemcpyAsync(out, c->G, sizeof(float) * 3 * c->g.N,
+                         hipMemcpyDeviceToDevice, c->stream));
+  return LMR_OK;
+}
+
+lmr_status lmr_get_state(lmr_ctx* c, lmr_pair_state* out) {
+  if (!c || !out) return LMR_EINVAL;
+  if (!c->begun) return LMR_ESTATE;
+  DevState h;
+  LMR_HIP(hipMemcpyAsync(&h, c->st, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  LMR_HIP(hipStreamSynchronize(c->stream));
+  out->lambda = h.lambda;
+  out->loss = h.loss;
+  out->loss_prev = h.loss_prev;
+  out->cand_loss = h.cand_loss;
+  out->n_hist = h.n_hist;
+  out->retries = h.retries;
+  out->accepted = h.accepted;
+  out->stalled = h.stalled;
+  out->attempts = h.attempts;
+  return LMR_OK;
+}
+
+lmr_status lmr_set_state(lmr_ctx* c, const lmr_pair_state* in) {
+  if (!c || !in) return LMR_EINVAL;
+  if (!c->begun) return LMR_ESTATE;
+  if (!(in->lambda > 0.0) || in->n_hist < 1 || in->retries < 0) return LMR_EINVAL;
+  DevState v{};
+  v.lambda = in->lambda;
+  v.loss = in->loss;
+  v.loss_prev = in->loss_prev;
+  v.cand_loss = in->cand_loss;
+  v.r = 1.0 + in->loss;
+  v.n_hist = in->n_hist;
+  v.retries = in->retries;
+  v.accepted = in->accepted;
+  v.stalled = in->stalled;
+  v.attempts = in->attempts;
+  LMR_HIP(launch_set_state(c->st, v, c->stream));
+  return LMR_OK;
+}
+
+lmr_status lmr_loss_grad(lmr_ctx* c, const void* F, const void* M, const float* u,
+                         double* loss_out, float* g_raw, float* g_smooth,
+                         float* cc_map) {
+  if (!c || !F || !M || !u) return LMR_EINVAL;
+  hipStream_t s = c->stream;
+  LMR_HIP(launch_warp(M, c->img, u, c->g, c->Mw, nullptr, s));
+  LMR_HIP(launch_fwd(F, c->img, c->Mw, c->g, c->p, nullptr, c->maps, c->partials,
+                     cc_map, s));
+  LMR_HIP(launch_decide(c->st, c->partials, c->nparts, c->g.N, c->dp, 2, -1, 0.0,
+                        c->probe, s));
+  if (g_raw || g_smooth) {
+    float* gr = g_raw ? g_raw : c->graw;
+    LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, nullptr, nullptr,
+                       nullptr, u, gr, s));
+    if (g_smooth) LMR_HIP(launch_smooth(gr, c->g, c->p, nullptr, g_smooth, s));
+  }
+  double L = 0.0;
+  LMR_HIP(hipMemcpyAsync(&L, c->probe, sizeof L, hipMemcpyDeviceToHost, s));
+  LMR_HIP(hipStreamSynchronize(s));
+  if (loss_out) *loss_out = L;
+  return LMR_OK;
+}
+
+lmr_status lmr_update(lmr_ctx* c, const float* u, const float* g_smooth, double r,
+                      double lambda, float* u_out) {
+  if (!c || !u || !g_smooth || !u_out || u == u_out) return LMR_EINVAL;
+  LMR_HIP(launch_update(nullptr, LMR_F32, c->g, c->p, nullptr, g_smooth, nullptr,
+                        nullptr, u, u_out, r, lambda, c->Mw, c->stream));
+  return LMR_OK;
+}
+
+lmr_status lmr_smooth(lmr_ctx* c, const float* g, float* out) {
+  if (!c || !g || !out || g == out) return LMR_EINVAL;
+  LMR_HIP(launch_smooth(g, c->g, c->p, nullptr, out, c->stream));
+  return LMR_OK;
+}
+
+lmr_status lmr_decide_probe(lmr_ctx* c, const lmr_pair_state* in, double cand_loss,
+                            int force, lmr_pair_state* out) {
+  if (!c || !in || !out || force < -1 || force > 1) return LMR_EINVAL;
+  DevState h{};
+  h.lambda = in->lambda;
+  h.loss = in->loss;
+  h.loss_prev = in->loss_prev;
+  h.cand_loss = in->cand_loss;
+  h.r = 1.0 + in->loss;
+  h.n_hist = in->n_hist;
+  h.retries = in->retries;
+  h.accepted = in->accepted;
+  h.stalled = in->stalled;
+  h.cur = 0;
+  h.attempts = in->attempts;
+  // one partial of -cand_loss over N = 1 reproduces cand_loss exactly
+  const double part = -cand_loss;
+  hipStream_t s = c->stream;
+  LMR_HIP(hipMemcpyAsync(c->st_probe, &h, sizeof h, hipMemcpyHostToDevice, s));
+  LMR_HIP(hipMemcpyAsync(c->part_probe, &part, sizeof part, hipMemcpyHostToDevice, s));
+  LMR_HIP(launch_decide(c->st_probe, c->part_probe, 1, 1, c->dp, 0, force, 0.0,
+                        nullptr, s));
+  LMR_HIP(hipMemcpyAsync(&h, c->st_probe, sizeof h, hipMemcpyDeviceToHost, s));
+  LMR_HIP(hipStreamSynchronize(s));
+  out->lambda = h.lambda;
+  out->loss = h.loss;
+  out->loss_prev = h.loss_prev;
+  out->cand_loss = h.cand_loss;
+  out->n_hist = h.n_hist;
+  out->retries = h.retries;
+  out->accepted = h.accepted;
+  out->stalled = h.stalled;
+  out->attempts = h.attempts;
+  return LMR_OK;
+}
+
+lmr_status lmr_warp(const void* M, lmr_dtype img, const float* u, int nz, int ny,
+                    int nx, float* Mw, float* dMw, hipStream_t stream) {
+  if (!M || !u || !Mw || nz < 1 || ny < 1 || nx < 1 || nz > 65535) return LMR_EINVAL;
+  if (img != LMR_F32 && img != LMR_BF16) return LMR_EINVAL;
+  long long N = (long long)nz * ny * nx;
+  if (N >= (1LL << 31)) return LMR_EINVAL;
+  LMR_HIP(launch_warp(M, img, u, Geom{nz, ny, nx, N}, Mw, dMw, stream));
+  return LMR_OK;
+}
+
+}  // extern "C"

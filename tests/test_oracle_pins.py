@@ -209,6 +209,20 @@ def test_grad_at_agrees_with_full_gradient(orc):
                                    g[:, z, y, x], rtol=1e-10, atol=1e-13)
 
 
+def test_point_evaluations_agree_with_volume_functions(orc):
+    shape = (8, 9, 10)
+    F, M = _smooth_pair(shape, 30)
+    u = _rng(31).uniform(-1.5, 1.5, (3,) + shape)
+    Mw = orc.warp(M, u)
+    _, cc = orc.lncc(F, Mw, 5, 1e-5, with_map=True)
+    g = _rng(32).standard_normal((3,) + shape)
+    gs = orc.gauss(g, 1.0)
+    for (z, y, x) in [(0, 0, 0), (3, 4, 5), (7, 8, 9), (0, 8, 2)]:
+        assert abs(orc.cc_at(F, M, u, 5, 1e-5, x, y, z) - cc[z, y, x]) < 1e-12
+        np.testing.assert_allclose(orc.gauss_at(g, 1.0, x, y, z), gs[:, z, y, x],
+                                   rtol=1e-12, atol=1e-14)
+
+
 # ------------------------------------------------------------------ O4 Gaussian
 @pytest.mark.parametrize("sigma", [1.0, 0.7, 1.6])
 def test_gauss_matches_scipy(orc, sigma):
