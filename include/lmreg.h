@@ -113,7 +113,8 @@ void lmr_default_params(lmr_params* p);
  * (about 80 bytes per voxel: field ping-pong, smoothed gradient, raw
  * gradient, four LNCC adjoint maps, warped image, reduction partials and the
  * device pair state); no later call allocates.  Sizes: each dimension >= 1,
- * nz*ny*nx < 2^31.  Errors: LMR_EINVAL (shape/params), LMR_ENOMEM. */
+ * nz*ny*nx < 2^30 (kernels address each channel with 32-bit byte offsets).
+ * Errors: LMR_EINVAL (shape/params), LMR_ENOMEM. */
 lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
                       const lmr_params* p, hipStream_t stream);
 void lmr_destroy(lmr_ctx* ctx);
@@ -179,6 +180,59 @@ lmr_status lmr_smooth(lmr_ctx* ctx, const float* g, float* out);
  * untouched.  Synchronises. */
 lmr_status lmr_decide_probe(lmr_ctx* ctx, const lmr_pair_state* in,
                             double cand_loss, int force, lmr_pair_state* out);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel timing.  While a profile is open, lmr_step records a HIP event pair
+ * on the context's stream around each kernel of every `stride`-th attempt
+ * (at most max_attempts attempts).  lmr_profile_stop synchronises and returns
+ * per-kernel count and duration statistics indexed by lmr_kernel. */
+typedef enum {
+  LMR_K_UPDATE = 0,  /* closed form + compositive integration + candidate warp */
+  LMR_K_FWD = 1,     /* LNCC forward (box sums, cc, adjoint maps, partials) */
+  LMR_K_DECIDE = 2,  /* FP64 loss reduction and decision */
+  LMR_K_BWD = 3,     /* LNCC backward and warp backward */
+  LMR_K_SMOOTH = 4,  /* Gaussian smoothing of the gradient */
+  LMR_NUM_KERNELS = 5
+} lmr_kernel;
+typedef struct {
+  int64_t count;
+  double total_ms, min_ms, max_ms;
+} lmr_kernel_time;
+lmr_status lmr_profile_start(lmr_ctx* ctx, int max_attempts, int stride);
+lmr_status lmr_profile_stop(lmr_ctx* ctx, lmr_kernel_time out[LMR_NUM_KERNELS]);
+const char* lmr_kernel_name(int kernel);
+
+/* ------------------------------------------------------------------------ */
+/* Coarse-to-fine registration (Sec. 2.1): level l works on images average-
+ * pooled by factors[l] (coarse to fine, each factor twice the next, the last
+ * one 1, every dimension divisible by factors[0]); level 0 starts from the
+ * identity, every later level from the previous field upsampled x2 (voxel-
+ * centre aligned, values doubled).  Lambda and the loss history restart at
+ * every level (losses of different resolutions are not comparable).  All
+ * level workspaces and pooled images (FP32) are allocated here. */
+typedef struct lmr_pyramid lmr_pyramid;
+lmr_status lmr_pyramid_create(lmr_pyramid** out, int nz, int ny, int nx,
+                              lmr_dtype img, const lmr_params* p, int nlevels,
+                              const int* factors, hipStream_t stream);
+/* Runs iters[l] attempts at every level (host array of nlevels counts) from
+ * lambda0 and writes the final field (device, [3][nz][ny][nx]).  decisions:
+ * NULL for automatic decisions, or a host array of sum(iters) forced
+ * decisions (level-major).  Enqueues only. */
+lmr_status lmr_pyramid_run(lmr_pyramid* pyr, const void* fixed, const void* moving,
+                           const int* iters, double lambda0, const int* decisions,
+                           float* field_out);
+/* The context of level l (borrowed; valid until lmr_pyramid_destroy). */
+lmr_ctx* lmr_pyramid_level(lmr_pyramid* pyr, int level);
+void lmr_pyramid_destroy(lmr_pyramid* pyr);
+
+/* Average pooling by f (every dimension divisible by f): out (device, FP32,
+ * [nz/f][ny/f][nx/f]) is the mean of each f^3 block of img. */
+lmr_status lmr_avgpool(const void* img, lmr_dtype t, int nz, int ny, int nx, int f,
+                       float* out, hipStream_t stream);
+/* x2 field upsampling of the pyramid: uc [3][nzc][nyc][nxc] ->
+ * uf [3][2nzc][2nyc][2nxc] (device). */
+lmr_status lmr_upsample_field(const float* uc, int nzc, int nyc, int nxc, float* uf,
+                              hipStream_t stream);
 
 /* Trilinear warp Mw(x) = M(x + u(x)), zero outside the volume; dMw (may be
  * NULL) receives d/dp M at x + u(x) as [3][nz][ny][nx].  Device arrays. */

@@ -65,6 +65,14 @@ class PairState(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class KernelTime(C.Structure):
+    """Mirror of lmr_kernel_time."""
+    _fields_ = [("count", C.c_int64), ("total_ms", C.c_double),
+                ("min_ms", C.c_double), ("max_ms", C.c_double)]
+
+
+KERNELS = ("update", "lncc_fwd", "decide", "lncc_bwd", "smooth")
+
 _lib = None
 _V, _I, _D, _LL = C.c_void_p, C.c_int, C.c_double, C.c_longlong
 
@@ -95,6 +103,17 @@ def lib() -> C.CDLL:
                                       C.POINTER(PairState)]),
             "lmr_smooth": (_I, [_V, _V, _V]),
             "lmr_set_state": (_I, [_V, C.POINTER(PairState)]),
+            "lmr_kernel_name": (C.c_char_p, [_I]),
+            "lmr_profile_start": (_I, [_V, _I, _I]),
+            "lmr_profile_stop": (_I, [_V, C.POINTER(KernelTime)]),
+            "lmr_avgpool": (_I, [_V, _I, _I, _I, _I, _I, _V, _V]),
+            "lmr_upsample_field": (_I, [_V, _I, _I, _I, _V, _V]),
+            "lmr_pyramid_create": (_I, [C.POINTER(_V), _I, _I, _I, _I,
+                                        C.POINTER(Params), _I, C.POINTER(_I), _V]),
+            "lmr_pyramid_run": (_I, [_V, _V, _V, C.POINTER(_I), _D, C.POINTER(_I),
+                                     _V]),
+            "lmr_pyramid_level": (_V, [_V, _I]),
+            "lmr_pyramid_destroy": (None, [_V]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -111,7 +130,10 @@ def exported_symbols():
             "lmr_destroy", "lmr_begin", "lmr_step", "lmr_step_forced",
             "lmr_get_field", "lmr_get_grad", "lmr_get_state", "lmr_loss_grad",
             "lmr_update", "lmr_warp", "lmr_decide_probe", "lmr_smooth",
-            "lmr_set_state"]
+            "lmr_set_state", "lmr_kernel_name", "lmr_profile_start",
+            "lmr_profile_stop", "lmr_avgpool", "lmr_upsample_field",
+            "lmr_pyramid_create", "lmr_pyramid_run", "lmr_pyramid_level",
+            "lmr_pyramid_destroy"]
 
 
 def _check(status: int, what: str):
@@ -208,6 +230,13 @@ class Context:
         _check(lib().lmr_get_state(self._h, C.byref(s)), "lmr_get_state")
         return s.as_dict()
 
+    def profile_start(self, max_attempts=1000, stride=1):
+        _check(lib().lmr_profile_start(self._h, int(max_attempts), int(stride)),
+               "lmr_profile_start")
+
+    def profile_stop(self) -> dict:
+        return _profile_stop(self._h)
+
     def set_state(self, state: dict):
         s = PairState(**{k: state.get(k, 0) for k, _ in PairState._fields_})
         _check(lib().lmr_set_state(self._h, C.byref(s)), "lmr_set_state")
@@ -262,3 +291,107 @@ def warp(M: torch.Tensor, u: torch.Tensor, with_grad=False, stream=None):
                           dMw.data_ptr() if with_grad else None,
                           _stream_handle(stream)), "lmr_warp")
     return (Mw, dMw) if with_grad else Mw
+
+
+def _profile_stop(h) -> dict:
+    arr = (KernelTime * len(KERNELS))()
+    _check(lib().lmr_profile_stop(h, arr), "lmr_profile_stop")
+    out = {}
+    for k, name in enumerate(KERNELS):
+        t = arr[k]
+        out[name] = dict(count=int(t.count), total_ms=t.total_ms, min_ms=t.min_ms,
+                         max_ms=t.max_ms,
+                         avg_ms=(t.total_ms / t.count) if t.count else float("nan"))
+    return out
+
+
+class LevelView:
+    """Borrowed view of one pyramid level's context."""
+
+    def __init__(self, handle, shape):
+        self._h = handle
+        self.shape = shape
+
+    def state(self) -> dict:
+        s = PairState()
+        _check(lib().lmr_get_state(self._h, C.byref(s)), "lmr_get_state")
+        return s.as_dict()
+
+    def profile_start(self, max_attempts=1000, stride=1):
+        _check(lib().lmr_profile_start(self._h, int(max_attempts), int(stride)),
+               "lmr_profile_start")
+
+    def profile_stop(self) -> dict:
+        return _profile_stop(self._h)
+
+
+class Pyramid:
+    """Coarse-to-fine registration (lmr_pyramid)."""
+
+    def __init__(self, shape, factors=(4, 2, 1), img_dtype=torch.float32,
+                 params: Params | None = None, stream=None, **kw):
+        self.shape = tuple(int(s) for s in shape)
+        self.factors = tuple(int(f) for f in factors)
+        self.img_dtype = img_dtype
+        self.params = params if params is not None else Params.make(**kw)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._h = _V()
+        fa = (C.c_int * len(self.factors))(*self.factors)
+        code = LMR_BF16 if img_dtype == torch.bfloat16 else LMR_F32
+        _check(lib().lmr_pyramid_create(C.byref(self._h), *self.shape, code,
+                                        C.byref(self.params), len(self.factors), fa,
+                                        _stream_handle(self.stream)),
+               "lmr_pyramid_create")
+
+    def close(self):
+        if self._h:
+            lib().lmr_pyramid_destroy(self._h)
+            self._h = _V()
+
+    __del__ = close
+
+    def level(self, l) -> LevelView:
+        h = lib().lmr_pyramid_level(self._h, int(l))
+        if not h:
+            raise LmrError(f"no level {l}")
+        f = self.factors[l]
+        return LevelView(C.c_void_p(h), tuple(s // f for s in self.shape))
+
+    def run(self, F, M, iters, lambda0=1.0, decisions=None, out=None):
+        f = _dev(F, self.shape, self.img_dtype, "fixed")
+        m = _dev(M, self.shape, self.img_dtype, "moving")
+        if len(iters) != len(self.factors):
+            raise LmrError("one iteration count per level is required")
+        it = (C.c_int * len(iters))(*[int(i) for i in iters])
+        dp = None
+        if decisions is not None:
+            if len(decisions) != sum(iters):
+                raise LmrError("decisions must hold sum(iters) entries")
+            dp = (C.c_int * len(decisions))(*[int(d) for d in decisions])
+        out = out if out is not None else torch.empty((3,) + self.shape, device="cuda")
+        _check(lib().lmr_pyramid_run(self._h, f, m, it, float(lambda0), dp,
+                                     _dev(out, (3,) + self.shape, torch.float32,
+                                          "out")), "lmr_pyramid_run")
+        return out
+
+
+def avgpool(img: torch.Tensor, f: int, stream=None) -> torch.Tensor:
+    shape = tuple(img.shape)
+    if len(shape) != 3 or any(s % f for s in shape):
+        raise LmrError("avgpool: [nz][ny][nx] divisible by f required")
+    p = _dev(img, shape, img.dtype, "img")
+    out = torch.empty(tuple(s // f for s in shape), device=img.device)
+    _check(lib().lmr_avgpool(p, _img_code(img), *shape, int(f), out.data_ptr(),
+                             _stream_handle(stream)), "lmr_avgpool")
+    return out
+
+
+def upsample_field(uc: torch.Tensor, stream=None) -> torch.Tensor:
+    if uc.dim() != 4 or uc.shape[0] != 3:
+        raise LmrError("upsample_field: [3][nz][ny][nx] required")
+    shape = tuple(uc.shape[1:])
+    p = _dev(uc, (3,) + shape, torch.float32, "uc")
+    out = torch.empty((3,) + tuple(2 * s for s in shape), device=uc.device)
+    _check(lib().lmr_upsample_field(p, *shape, out.data_ptr(), _stream_handle(stream)),
+           "lmr_upsample_field")
+    return out

@@ -6,12 +6,24 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "lmr_internal.h"
 
 using namespace lmr;
 
+// Event pairs recorded around the kernels of sampled attempts.
+struct Profiler {
+  bool on = false;
+  int stride = 1;
+  int max_attempts = 0;
+  int recorded = 0;   // attempts recorded
+  long long seen = 0; // attempts enqueued while on
+  std::vector<hipEvent_t> ev;  // 2 * LMR_NUM_KERNELS per recorded attempt
+};
+
 struct lmr_ctx {
+  Profiler prof;
   Geom g;
   lmr_dtype img;
   lmr_params p;
@@ -65,16 +77,42 @@ size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 // One attempt: P1 update, P2 forward, P3 decide, P4 backward, P5 smooth.
 lmr_status enqueue_attempt(lmr_ctx* c, const void* F, const void* M, int force) {
   hipStream_t s = c->stream;
+  Profiler& pr = c->prof;
+  hipEvent_t* ev = nullptr;
+  if (pr.on) {
+    if (pr.seen % pr.stride == 0 && pr.recorded < pr.max_attempts)
+      ev = &pr.ev[2 * LMR_NUM_KERNELS * pr.recorded++];
+    ++pr.seen;
+  }
+  auto mark = [&](int k, int end) -> hipError_t {
+    return ev ? hipEventRecord(ev[2 * k + end], s) : hipSuccess;
+  };
+  LMR_HIP(mark(LMR_K_UPDATE, 0));
   LMR_HIP(launch_update(M, c->img, c->g, c->p, c->st, c->G, c->U[0], c->U[1], nullptr,
                         nullptr, 0.0, 0.0, c->Mw, s));
+  LMR_HIP(mark(LMR_K_UPDATE, 1));
+  LMR_HIP(mark(LMR_K_FWD, 0));
   LMR_HIP(launch_fwd(F, c->img, c->Mw, c->g, c->p, c->st, c->maps, c->partials,
                      nullptr, s));
+  LMR_HIP(mark(LMR_K_FWD, 1));
+  LMR_HIP(mark(LMR_K_DECIDE, 0));
   LMR_HIP(launch_decide(c->st, c->partials, c->nparts, c->g.N, c->dp, 0, force, 0.0,
                         nullptr, s));
+  LMR_HIP(mark(LMR_K_DECIDE, 1));
+  LMR_HIP(mark(LMR_K_BWD, 0));
   LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, c->st, c->U[0], c->U[1],
                      nullptr, c->graw, s));
+  LMR_HIP(mark(LMR_K_BWD, 1));
+  LMR_HIP(mark(LMR_K_SMOOTH, 0));
   LMR_HIP(launch_smooth(c->graw, c->g, c->p, c->st, c->G, s));
+  LMR_HIP(mark(LMR_K_SMOOTH, 1));
   return LMR_OK;
+}
+
+void profile_release(Profiler& pr) {
+  for (hipEvent_t e : pr.ev) (void)hipEventDestroy(e);
+  pr.ev.clear();
+  pr.on = false;
 }
 
 }  // namespace
@@ -117,7 +155,7 @@ lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
   *out = nullptr;
   if (nz < 1 || ny < 1 || nx < 1 || nz > 65535) return LMR_EINVAL;
   long long N = (long long)nz * ny * nx;
-  if (N >= (1LL << 31)) return LMR_EINVAL;
+  if (N >= (1LL << 30)) return LMR_EINVAL;
   if (img != LMR_F32 && img != LMR_BF16) return LMR_EINVAL;
   if (!params_ok(p)) return LMR_EINVAL;
 
@@ -171,6 +209,7 @@ lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
 void lmr_destroy(lmr_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  profile_release(c->prof);
   (void)hipFree(c->arena);
   delete c;
 }
@@ -348,9 +387,199 @@ lmr_status lmr_warp(const void* M, lmr_dtype img, const float* u, int nz, int ny
   if (!M || !u || !Mw || nz < 1 || ny < 1 || nx < 1 || nz > 65535) return LMR_EINVAL;
   if (img != LMR_F32 && img != LMR_BF16) return LMR_EINVAL;
   long long N = (long long)nz * ny * nx;
-  if (N >= (1LL << 31)) return LMR_EINVAL;
+  if (N >= (1LL << 30)) return LMR_EINVAL;
   LMR_HIP(launch_warp(M, img, u, Geom{nz, ny, nx, N}, Mw, dMw, stream));
   return LMR_OK;
+}
+
+// ------------------------------------------------------------ kernel timing
+const char* lmr_kernel_name(int k) {
+  static const char* names[LMR_NUM_KERNELS] = {"update", "lncc_fwd", "decide",
+                                               "lncc_bwd", "smooth"};
+  return (k >= 0 && k < LMR_NUM_KERNELS) ? names[k] : "unknown";
+}
+
+lmr_status lmr_profile_start(lmr_ctx* c, int max_attempts, int stride) {
+  if (!c || max_attempts < 1 || stride < 1) return LMR_EINVAL;
+  profile_release(c->prof);
+  Profiler& pr = c->prof;
+  pr.ev.resize(2 * LMR_NUM_KERNELS * (size_t)max_attempts);
+  for (auto& e : pr.ev) {
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) {
+      e = nullptr;
+      profile_release(pr);
+      return hip_fail(err);
+    }
+  }
+  pr.on = true;
+  pr.stride = stride;
+  pr.max_attempts = max_attempts;
+  pr.recorded = 0;
+  pr.seen = 0;
+  return LMR_OK;
+}
+
+lmr_status lmr_profile_stop(lmr_ctx* c, lmr_kernel_time out[LMR_NUM_KERNELS]) {
+  if (!c || !out) return LMR_EINVAL;
+  Profiler& pr = c->prof;
+  if (!pr.on) return LMR_ESTATE;
+  for (int k = 0; k < LMR_NUM_KERNELS; ++k) out[k] = lmr_kernel_time{0, 0.0, 0.0, 0.0};
+  hipError_t err = hipStreamSynchronize(c->stream);
+  if (err != hipSuccess) {
+    profile_release(pr);
+    return hip_fail(err);
+  }
+  for (int a = 0; a < pr.recorded; ++a)
+    for (int k = 0; k < LMR_NUM_KERNELS; ++k) {
+      float ms = 0.0f;
+      hipEvent_t* e = &pr.ev[2 * LMR_NUM_KERNELS * a + 2 * k];
+      if (hipEventElapsedTime(&ms, e[0], e[1]) != hipSuccess) continue;
+      lmr_kernel_time& t = out[k];
+      if (t.count == 0 || ms < t.min_ms) t.min_ms = ms;
+      if (ms > t.max_ms) t.max_ms = ms;
+      t.total_ms += ms;
+      t.count += 1;
+    }
+  profile_release(pr);
+  return LMR_OK;
+}
+
+// ---------------------------------------------------------------- pyramid
+lmr_status lmr_avgpool(const void* img, lmr_dtype t, int nz, int ny, int nx, int f,
+                       float* out, hipStream_t stream) {
+  if (!img || !out || f < 1 || nz < 1 || ny < 1 || nx < 1) return LMR_EINVAL;
+  if (t != LMR_F32 && t != LMR_BF16) return LMR_EINVAL;
+  if (nz % f || ny % f || nx % f) return LMR_EINVAL;
+  LMR_HIP(launch_avgpool(img, t, nz, ny, nx, f, out, stream));
+  return LMR_OK;
+}
+
+lmr_status lmr_upsample_field(const float* uc, int nzc, int nyc, int nxc, float* uf,
+                              hipStream_t stream) {
+  if (!uc || !uf || nzc < 1 || nyc < 1 || nxc < 1) return LMR_EINVAL;
+  if (8LL * nzc * nyc * nxc >= (1LL << 30)) return LMR_EINVAL;
+  LMR_HIP(launch_upsample_field(uc, nzc, nyc, nxc, uf, stream));
+  return LMR_OK;
+}
+
+}  // extern "C"
+
+struct lmr_pyramid {
+  int nlevels;
+  int factors[8];
+  int dims[8][3];
+  lmr_dtype img;
+  hipStream_t stream;
+  lmr_ctx* lv[8];
+  float* Fl[8];   // pooled fixed image (null at factor 1)
+  float* Ml[8];   // pooled moving image
+  float* ul[8];   // field handed to level l
+  void* arena;
+};
+
+extern "C" {
+
+void lmr_pyramid_destroy(lmr_pyramid* y) {
+  if (!y) return;
+  for (int l = 0; l < y->nlevels; ++l) lmr_destroy(y->lv[l]);
+  (void)hipFree(y->arena);
+  delete y;
+}
+
+lmr_status lmr_pyramid_create(lmr_pyramid** out, int nz, int ny, int nx, lmr_dtype img,
+                              const lmr_params* p, int nlevels, const int* factors,
+                              hipStream_t stream) {
+  if (!out || !factors || nlevels < 1 || nlevels > 8) return LMR_EINVAL;
+  *out = nullptr;
+  if (factors[nlevels - 1] != 1) return LMR_EINVAL;
+  for (int l = 0; l + 1 < nlevels; ++l)
+    if (factors[l] != 2 * factors[l + 1]) return LMR_EINVAL;
+  const int f0 = factors[0];
+  if (nz < 1 || ny < 1 || nx < 1 || nz % f0 || ny % f0 || nx % f0) return LMR_EINVAL;
+  if (!params_ok(p)) return LMR_EINVAL;
+  lmr_pyramid* y = new (std::nothrow) lmr_pyramid();
+  if (!y) return LMR_ENOMEM;
+  y->nlevels = nlevels;
+  y->img = img;
+  y->stream = stream;
+  size_t total = 0;
+  for (int l = 0; l < nlevels; ++l) {
+    const int f = factors[l];
+    y->factors[l] = f;
+    y->dims[l][0] = nz / f;
+    y->dims[l][1] = ny / f;
+    y->dims[l][2] = nx / f;
+    const size_t n = (size_t)(nz / f) * (ny / f) * (nx / f);
+    total += align256(4 * 3 * n) + (f > 1 ? 2 * align256(4 * n) : 0);
+  }
+  if (hipMalloc(&y->arena, total) != hipSuccess) {
+    delete y;
+    return LMR_ENOMEM;
+  }
+  char* q = static_cast<char*>(y->arena);
+  for (int l = 0; l < nlevels; ++l) {
+    const size_t n = (size_t)y->dims[l][0] * y->dims[l][1] * y->dims[l][2];
+    y->ul[l] = reinterpret_cast<float*>(q);
+    q += align256(4 * 3 * n);
+    y->Fl[l] = y->Ml[l] = nullptr;
+    if (factors[l] > 1) {
+      y->Fl[l] = reinterpret_cast<float*>(q);
+      q += align256(4 * n);
+      y->Ml[l] = reinterpret_cast<float*>(q);
+      q += align256(4 * n);
+    }
+    lmr_status st = lmr_create(&y->lv[l], y->dims[l][0], y->dims[l][1], y->dims[l][2],
+                               factors[l] > 1 ? LMR_F32 : img, p, stream);
+    if (st != LMR_OK) {
+      y->nlevels = l;
+      lmr_pyramid_destroy(y);
+      return st;
+    }
+  }
+  *out = y;
+  return LMR_OK;
+}
+
+lmr_ctx* lmr_pyramid_level(lmr_pyramid* y, int l) {
+  return (y && l >= 0 && l < y->nlevels) ? y->lv[l] : nullptr;
+}
+
+lmr_status lmr_pyramid_run(lmr_pyramid* y, const void* F, const void* M,
+                           const int* iters, double lambda0, const int* decisions,
+                           float* field_out) {
+  if (!y || !F || !M || !iters || !field_out || !(lambda0 > 0.0)) return LMR_EINVAL;
+  for (int l = 0; l < y->nlevels; ++l)
+    if (iters[l] < 0) return LMR_EINVAL;
+  const int* d = decisions;
+  const int* fine = y->dims[y->nlevels - 1];
+  for (int l = 0; l < y->nlevels; ++l) {
+    lmr_ctx* c = y->lv[l];
+    const void* Fl = F;
+    const void* Ml = M;
+    if (y->factors[l] > 1) {
+      LMR_HIP(launch_avgpool(F, y->img, fine[0], fine[1], fine[2], y->factors[l], y->Fl[l],
+                             y->stream));
+      LMR_HIP(launch_avgpool(M, y->img, fine[0], fine[1], fine[2], y->factors[l], y->Ml[l],
+                             y->stream));
+      Fl = y->Fl[l];
+      Ml = y->Ml[l];
+    }
+    const float* u0 = nullptr;
+    if (l > 0) {
+      lmr_status st = lmr_get_field(y->lv[l - 1], y->ul[l - 1]);
+      if (st != LMR_OK) return st;
+      LMR_HIP(launch_upsample_field(y->ul[l - 1], y->dims[l - 1][0], y->dims[l - 1][1],
+                                    y->dims[l - 1][2], y->ul[l], y->stream));
+      u0 = y->ul[l];
+    }
+    lmr_status st = lmr_begin(c, Fl, Ml, u0, lambda0);
+    if (st != LMR_OK) return st;
+    st = d ? lmr_step_forced(c, Fl, Ml, d, iters[l]) : lmr_step(c, Fl, Ml, iters[l]);
+    if (st != LMR_OK) return st;
+    if (d) d += iters[l];
+  }
+  return lmr_get_field(y->lv[y->nlevels - 1], field_out);
 }
 
 }  // extern "C"

@@ -1,130 +1,179 @@
 // Separable 3D stencils of one LM attempt, on a shared 2.5D framework.
 //
-//   k_fwd     LNCC forward: box sums of F, Mw, F^2, Mw^2, F Mw over the w^3
+//   lncc_fwd  LNCC forward: box sums of F, Mw, F^2, Mw^2, F Mw over the w^3
 //             window (zero padding, divisor w^3), cc = s_FM^2/(s_FF s_MM + eps),
 //             adjoint maps alpha = 2 s_FM/D, alpha mu_F, beta = -s_FM^2 s_FF/D^2,
 //             beta mu_M, and one FP64 partial sum of cc per block.
-//   k_bwd     LNCC backward: box sums of the four maps give
+//   lncc_bwd  LNCC backward: box sums of the four maps give
 //             d(sum cc)/dMw_j = (F_j B(alpha) - B(alpha mu_F) + 2 Mw_j B(beta)
 //                                - 2 B(beta mu_M)) / w^3,
 //             times the trilinear derivative of M at x + u(x) (warp backward);
 //             the result is g = N dL/du with L = -mean cc.
-//   k_smooth  Gaussian of the raw gradient (Eulerian descent, Sec. 2.1).
+//   smooth    Gaussian of the raw gradient (Eulerian descent, Sec. 2.1).
 //
-// Framework: a block owns a TX x TY column of outputs and marches along z
+// Framework: a block owns a 32 x TY column of outputs and marches along z
 // through a chunk of cz planes.  For each input plane it stages a
-// (TY+2R) x (TX+2R) halo tile of the input channels in LDS, reduces along y
-// then along x in LDS, and keeps the last 2R+1 plane sums in registers, whose
-// weighted sum is the output plane R steps behind.  Box sums accumulate exact
-// FP32 products in FP64.
+// (TY+2R) x (32+2R) halo tile of the raw FP32 inputs in LDS (the next plane is
+// already in flight in registers while the current one is reduced), reduces
+// along y (expanding the raw inputs into the accumulated channels: for the
+// forward pass the exact products F^2, Mw^2, F Mw in FP64) and then along x,
+// and keeps the last 2R+1 plane sums in a register ring.  Box sums run a
+// running sum through the ring; weighted stencils sum it with their taps.
 #include "lmr_internal.h"
 
 namespace lmr {
 
 namespace {
 
-constexpr int kTX = 32, kTY = 8;
+constexpr int kTX = 32;
+// element index whose byte offset lies beyond any channel (< 2^30 voxels)
+constexpr unsigned kFarIndex = 0x3FFFFFFFu;
 
 struct Tiling {
-  int tiles_x, tiles_y, nchunks, cz;
+  int ty, tiles_x, tiles_y, nchunks, cz;
   int blocks() const { return tiles_x * tiles_y * nchunks; }
 };
 
-// Choose the z-chunk so that the launch has enough blocks to fill 256 CUs
-// several times over while the z halo (2R extra planes per chunk) stays small.
-Tiling make_tiling(const Geom& g) {
+// z-chunk: long enough that the 2R halo planes of a chunk stay a small
+// fraction when the volume is large, short enough that small volumes still
+// give the launch a few hundred blocks.
+Tiling make_tiling(const Geom& g, int ty) {
   Tiling t;
+  t.ty = ty;
   t.tiles_x = (g.nx + kTX - 1) / kTX;
-  t.tiles_y = (g.ny + kTY - 1) / kTY;
-  int tiles = t.tiles_x * t.tiles_y;
-  int want = (2048 + tiles - 1) / tiles;
+  t.tiles_y = (g.ny + ty - 1) / ty;
+  const int tiles = t.tiles_x * t.tiles_y;
+  const int want = (2048 + tiles - 1) / tiles;
   int cz = (g.nz + want - 1) / want;
-  if (cz < 16) cz = 16;
+  if (tiles * ((g.nz + 15) / 16) >= 1024 && cz < 16) cz = 16;
+  if (cz < 4) cz = 4;
   if (cz > g.nz) cz = g.nz;
   t.cz = cz;
   t.nchunks = (g.nz + cz - 1) / cz;
   return t;
 }
 
-template <int R, class P>
-__global__ void __launch_bounds__(kTX* kTY)
+template <int R, int TY, class P>
+__global__ void __launch_bounds__(kTX* TY)
     k_stencil(const P pol, Geom g, int cz, int tiles_x, int tiles_y) {
   using A = typename P::Acc;
-  constexpr int NC = P::NCH;
-  constexpr int W = 2 * R + 1, LX = kTX + 2 * R, LY = kTY + 2 * R, NT = kTX * kTY;
-  __shared__ A s_in[NC][LY][LX];
-  __shared__ A s_y[NC][kTY][LX];
+  constexpr int NR = P::NRAW, NC = P::NCH;
+  constexpr int W = 2 * R + 1, LX = kTX + 2 * R, LY = TY + 2 * R, NT = kTX * TY;
+  constexpr int NPOS = LX * LY, PER = (NPOS + NT - 1) / NT;
+  __shared__ float s_in[NR][LY][LX];
+  __shared__ A s_y[NC][TY][LX];
 
   if (!pol.active()) return;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int tx_i = b % tiles_x;
   const int ty_i = (b / tiles_x) % tiles_y;
   const int ch = b / (tiles_x * tiles_y);
-  const int x0 = tx_i * kTX, y0 = ty_i * kTY, z0 = ch * cz;
+  const int x0 = tx_i * kTX, y0 = ty_i * TY, z0 = ch * cz;
   const int z1 = min(z0 + cz, g.nz);
   const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
   const int gx = x0 + lx, gy = y0 + ly;
   const bool own = gx < g.nx && gy < g.ny;
+  const int plane = g.ny * g.nx;
 
-  A ring[W][NC];
+  // positions of the halo tile this thread stages, and their raw values
+  int pidx[PER];
+  bool pin[PER];
 #pragma unroll
-  for (int k = 0; k < W; ++k)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) ring[k][c] = A(0);
+  for (int p = 0; p < PER; ++p) {
+    const int i = threadIdx.x + p * NT;
+    const int yy = i / LX, xx = i - yy * LX;
+    const int gyy = y0 - R + yy, gxx = x0 - R + xx;
+    pin[p] = i < NPOS && (unsigned)gyy < (unsigned)g.ny && (unsigned)gxx < (unsigned)g.nx;
+    pidx[p] = pin[p] ? gyy * g.nx + gxx : 0;
+  }
   typename P::Local loc = pol.begin_block();
-
-  for (int zi = z0 - R; zi < z1 + R; ++zi) {
-    const bool zin = zi >= 0 && zi < g.nz;
-    for (int i = threadIdx.x; i < LY * LX; i += NT) {
-      const int yy = i / LX, xx = i - yy * LX;
-      const int gyy = y0 - R + yy, gxx = x0 - R + xx;
-      A v[NC];
-      if (zin && (unsigned)gyy < (unsigned)g.ny && (unsigned)gxx < (unsigned)g.nx) {
-        pol.load(((long long)zi * g.ny + gyy) * g.nx + gxx, v);
-      } else {
+  // Branch-free staging: a padding position reads kFarIndex and a plane
+  // outside the volume wraps beyond the buffer; both read 0.
+  float pre[PER][NR];
+  auto fetch = [&](int zi) {
+    const unsigned zoff = static_cast<unsigned>(zi * plane);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) v[c] = A(0);
+    for (int p = 0; p < PER; ++p)
+      pol.load(loc, pin[p] ? zoff + static_cast<unsigned>(pidx[p]) : kFarIndex, pre[p]);
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int i = threadIdx.x + p * NT;
+      if (i < NPOS) {
+        const int yy = i / LX, xx = i - yy * LX;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) s_in[c][yy][xx] = pre[p][c];
       }
-#pragma unroll
-      for (int c = 0; c < NC; ++c) s_in[c][yy][xx] = v[c];
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kTY * LX; i += NT) {
-      const int yy = i / LX, xx = i - yy * LX;
-      A a[NC];
+  };
+
+  A ring[W][NC], run[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) a[c] = A(0);
+  for (int c = 0; c < NC; ++c) {
+    run[c] = A(0);
 #pragma unroll
-      for (int k = 0; k < W; ++k)
+    for (int k = 0; k < W; ++k) ring[k][c] = A(0);
+  }
+
+  const int zend = z1 + R;
+  int zi = z0 - R;
+  fetch(zi);
+  while (zi < zend) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) a[c] += pol.wt(k) * s_in[c][yy + k][xx];
+    for (int s = 0; s < W; ++s) {
+      if (zi < zend) {
+        commit();
+        if (zi + 1 < zend) fetch(zi + 1);
+        __syncthreads();
+        for (int i = threadIdx.x; i < TY * LX; i += NT) {
+          const int yy = i / LX, xx = i - yy * LX;
+          A a[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) s_y[c][yy][xx] = a[c];
-    }
-    __syncthreads();
-    A pl[NC];
+          for (int c = 0; c < NC; ++c) a[c] = A(0);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) pl[c] = A(0);
+          for (int k = 0; k < W; ++k) {
+            float r[NR];
 #pragma unroll
-    for (int k = 0; k < W; ++k)
+            for (int c = 0; c < NR; ++c) r[c] = s_in[c][yy + k][xx];
+            pol.accum(a, r, k);
+          }
 #pragma unroll
-      for (int c = 0; c < NC; ++c) pl[c] += pol.wt(k) * s_y[c][ly][lx + k];
+          for (int c = 0; c < NC; ++c) s_y[c][yy][xx] = a[c];
+        }
+        __syncthreads();
+        A pl[NC];
 #pragma unroll
-    for (int k = 0; k < W - 1; ++k)
+        for (int c = 0; c < NC; ++c) pl[c] = A(0);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) ring[k][c] = ring[k + 1][c];
+        for (int k = 0; k < W; ++k)
 #pragma unroll
-    for (int c = 0; c < NC; ++c) ring[W - 1][c] = pl[c];
-    const int zo = zi - R;
-    if (zo >= z0 && own) {
-      A sm[NC];
+          for (int c = 0; c < NC; ++c) pl[c] += pol.wt(k) * s_y[c][ly][lx + k];
+        A sm[NC];
+        if (P::kBox) {
+          // ring[s] holds the plane that entered W steps ago
 #pragma unroll
-      for (int c = 0; c < NC; ++c) sm[c] = A(0);
+          for (int c = 0; c < NC; ++c) {
+            run[c] += pl[c] - ring[s][c];
+            ring[s][c] = pl[c];
+            sm[c] = run[c];
+          }
+        } else {
 #pragma unroll
-      for (int k = 0; k < W; ++k)
+          for (int c = 0; c < NC; ++c) {
+            ring[s][c] = pl[c];
+            sm[c] = A(0);
+          }
+          // planes zi-2R .. zi sit in slots s+1 .. s+W (mod W)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sm[c] += pol.wt(k) * ring[k][c];
-      pol.emit(loc, ((long long)zo * g.ny + gy) * g.nx + gx, gx, gy, zo, sm);
+          for (int k = 0; k < W; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sm[c] += pol.wt(k) * ring[(s + 1 + k) % W][c];
+        }
+        const int zo = zi - R;
+        if (zo >= z0 && own) pol.emit(loc, zo * plane + gy * g.nx + gx, gx, gy, zo, sm);
+      }
+      ++zi;
     }
   }
   pol.end_block(loc);
@@ -148,34 +197,42 @@ __device__ __forceinline__ void block_sum_to(double v, double* out) {
 }
 
 // ------------------------------------------------------------- forward (P2)
-template <typename T>
+template <typename T, int NT>
 struct FwdPol {
   using Acc = double;
-  static constexpr int NCH = 5;
+  static constexpr int NRAW = 2, NCH = 5;
+  static constexpr bool kBox = true;
   const T* __restrict__ F;
   const float* __restrict__ Mw;
   float* __restrict__ maps;
   float* __restrict__ cc;
   double* __restrict__ partials;
   const DevState* st;
-  long long N;
+  int N;
   double inv_n, eps;
   struct Local {
     double sum;
+    RBuf bF, bM;
   };
 
   __device__ bool active() const { return !st || !st->stalled; }
   __device__ static constexpr double wt(int) { return 1.0; }
-  __device__ Local begin_block() const { return Local{0.0}; }
-  __device__ void load(long long i, double v[5]) const {
-    const double f = ldf(F, i), m = Mw[i];
-    v[0] = f;
-    v[1] = m;
-    v[2] = f * f;
-    v[3] = m * m;
-    v[4] = f * m;
+  __device__ Local begin_block() const {
+    return Local{0.0, make_rbuf_n(F, N), make_rbuf_n(Mw, N)};
   }
-  __device__ void emit(Local& loc, long long i, int, int, int, const double S[5]) const {
+  __device__ void load(const Local& l, unsigned i, float v[2]) const {
+    v[0] = bld<T>(l.bF, i);
+    v[1] = bld<float>(l.bM, i);
+  }
+  __device__ void accum(double a[5], const float r[2], int) const {
+    const double f = r[0], m = r[1];
+    a[0] += f;
+    a[1] += m;
+    a[2] = fma(f, f, a[2]);
+    a[3] = fma(m, m, a[3]);
+    a[4] = fma(f, m, a[4]);
+  }
+  __device__ void emit(Local& loc, int i, int, int, int, const double S[5]) const {
     const double muF = S[0] * inv_n, muM = S[1] * inv_n;
     const double sfm = S[4] * inv_n - muF * muM;
     const double sff = S[2] * inv_n - muF * muF;
@@ -191,16 +248,15 @@ struct FwdPol {
     if (cc) cc[i] = static_cast<float>(c);
     loc.sum += c;
   }
-  __device__ void end_block(const Local& loc) const {
-    block_sum_to<kTX * kTY>(loc.sum, partials);
-  }
+  __device__ void end_block(const Local& loc) const { block_sum_to<NT>(loc.sum, partials); }
 };
 
 // ------------------------------------------------------------ backward (P4)
 template <typename T>
 struct BwdPol {
   using Acc = double;
-  static constexpr int NCH = 4;
+  static constexpr int NRAW = 4, NCH = 4;
+  static constexpr bool kBox = true;
   const T* __restrict__ F;
   const T* __restrict__ M;
   const float* __restrict__ Mw;
@@ -214,30 +270,43 @@ struct BwdPol {
   double inv_n;
   struct Local {
     const float* u;
+    RBuf bmap[4];
+    RBuf bM;
   };
 
   __device__ bool active() const { return !st || (!st->stalled && st->accepted); }
   __device__ static constexpr double wt(int) { return 1.0; }
   __device__ Local begin_block() const {
-    return Local{st ? (st->cur ? U1 : U0) : u_explicit};
+    const int N = static_cast<int>(g.N);
+    Local l;
+    l.u = st ? (st->cur ? U1 : U0) : u_explicit;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) l.bmap[c] = make_rbuf_n(maps + c * N, N);
+    l.bM = make_rbuf_n(M, N);
+    return l;
   }
-  __device__ void load(long long i, double v[4]) const {
-    v[0] = maps[i];
-    v[1] = maps[g.N + i];
-    v[2] = maps[2 * g.N + i];
-    v[3] = maps[3 * g.N + i];
+  __device__ void load(const Local& l, unsigned i, float v[4]) const {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = bld<float>(l.bmap[c], i);
   }
-  __device__ void emit(const Local& loc, long long i, int x, int y, int z,
+  __device__ void accum(double a[4], const float r[4], int) const {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] += static_cast<double>(r[c]);
+  }
+  __device__ void emit(const Local& loc, int i, int x, int y, int z,
                        const double B[4]) const {
+    const int N = static_cast<int>(g.N);
     const float* u = loc.u;
     const double fj = ldf(F, i), mj = Mw[i];
     const double dS = (fj * B[0] - B[1] + 2.0 * mj * B[2] - 2.0 * B[3]) * inv_n;
     const float d = static_cast<float>(dS);
-    float gm[3];
-    trilinear(M, g, x, y, z, u[i], u[g.N + i], u[2 * g.N + i], gm);
+    float gm[3], v[8];
+    const BCell c = make_bcell(g, x, y, z, u[i], u[N + i], u[2 * N + i]);
+    bcorners<T>(loc.bM, g, c, v);
+    binterp(c, v, gm);
     graw[i] = -d * gm[0];
-    graw[g.N + i] = -d * gm[1];
-    graw[2 * g.N + i] = -d * gm[2];
+    graw[N + i] = -d * gm[1];
+    graw[2 * N + i] = -d * gm[2];
   }
   __device__ void end_block(const Local&) const {}
 };
@@ -246,23 +315,31 @@ struct BwdPol {
 template <int R>
 struct SmoothPol {
   using Acc = float;
-  static constexpr int NCH = 3;
+  static constexpr int NRAW = 3, NCH = 3;
+  static constexpr bool kBox = false;
   const float* __restrict__ in;
   float* __restrict__ out;
   const DevState* st;
-  long long N;
+  int N;
   float w[2 * R + 1];
-  struct Local {};
+  struct Local {
+    RBuf b[3];
+  };
 
   __device__ bool active() const { return !st || (!st->stalled && st->accepted); }
   __device__ float wt(int k) const { return w[k]; }
-  __device__ Local begin_block() const { return Local{}; }
-  __device__ void load(long long i, float v[3]) const {
-    v[0] = in[i];
-    v[1] = in[N + i];
-    v[2] = in[2 * N + i];
+  __device__ Local begin_block() const {
+    return Local{{make_rbuf_n(in, N), make_rbuf_n(in + N, N), make_rbuf_n(in + 2 * N, N)}};
   }
-  __device__ void emit(Local&, long long i, int, int, int, const float S[3]) const {
+  __device__ void load(const Local& l, unsigned i, float v[3]) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = bld<float>(l.b[c], i);
+  }
+  __device__ void accum(float a[3], const float r[3], int k) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a[c] += w[k] * r[c];
+  }
+  __device__ void emit(Local&, int i, int, int, int, const float S[3]) const {
     out[i] = S[0];
     out[N + i] = S[1];
     out[2 * N + i] = S[2];
@@ -270,11 +347,13 @@ struct SmoothPol {
   __device__ void end_block(const Local&) const {}
 };
 
+constexpr int kTY = 8;
+
 template <class P, int R>
 hipError_t run(const P& pol, const Geom& g, hipStream_t s) {
-  Tiling t = make_tiling(g);
-  hipLaunchKernelGGL((k_stencil<R, P>), dim3(t.blocks()), dim3(kTX * kTY), 0, s, pol,
-                     g, t.cz, t.tiles_x, t.tiles_y);
+  Tiling t = make_tiling(g, kTY);
+  hipLaunchKernelGGL((k_stencil<R, kTY, P>), dim3(t.blocks()), dim3(kTX * kTY), 0, s,
+                     pol, g, t.cz, t.tiles_x, t.tiles_y);
   return hipGetLastError();
 }
 
@@ -293,16 +372,15 @@ template <typename T>
 hipError_t fwd_t(const T* F, const float* Mw, const Geom& g, const lmr_params& p,
                  const DevState* st, float* maps, double* partials, float* cc,
                  hipStream_t s) {
-  FwdPol<T> pol;
+  FwdPol<T, kTX * kTY> pol;
   pol.F = F;
   pol.Mw = Mw;
   pol.maps = maps;
   pol.cc = cc;
   pol.partials = partials;
   pol.st = st;
-  pol.N = g.N;
-  const double n = (double)p.window * p.window * p.window;
-  pol.inv_n = 1.0 / n;
+  pol.N = static_cast<int>(g.N);
+  pol.inv_n = 1.0 / ((double)p.window * p.window * p.window);
   pol.eps = p.cc_eps;
   return run_box(pol, p.window, g, s);
 }
@@ -334,7 +412,7 @@ hipError_t smooth_r(const float* in, float* out, const Geom& g, double sigma,
   pol.in = in;
   pol.out = out;
   pol.st = st;
-  pol.N = g.N;
+  pol.N = static_cast<int>(g.N);
   double w[2 * R + 1], tot = 0.0;
   for (int k = -R; k <= R; ++k) {
     w[k + R] = R == 0 ? 1.0 : exp(-(double)k * k / (2.0 * sigma * sigma));
@@ -346,7 +424,7 @@ hipError_t smooth_r(const float* in, float* out, const Geom& g, double sigma,
 
 }  // namespace
 
-int fwd_num_blocks(const Geom& g, int) { return make_tiling(g).blocks(); }
+int fwd_num_blocks(const Geom& g, int) { return make_tiling(g, kTY).blocks(); }
 
 int gauss_radius(double sigma) {
   if (!(sigma > 0.0)) return 0;

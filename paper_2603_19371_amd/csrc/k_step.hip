@@ -16,70 +16,31 @@ namespace {
 
 constexpr int kBX = 64, kBY = 4;
 
-__device__ __forceinline__ bool voxel(const Geom& g, int& x, int& y, int& z,
-                                      long long& i) {
+__device__ __forceinline__ bool voxel(const Geom& g, int& x, int& y, int& z, int& i) {
   x = blockIdx.x * kBX + threadIdx.x;
   y = blockIdx.y * kBY + threadIdx.y;
   z = blockIdx.z;
   if (x >= g.nx || y >= g.ny) return false;
-  i = ((long long)z * g.ny + y) * g.nx + x;
+  i = (z * g.ny + y) * g.nx + x;
   return true;
-}
-
-// Trilinear sample of the three field components at one point (shared cell).
-__device__ __forceinline__ void trilinear3(const float* __restrict__ U, const Geom& g,
-                                           int x, int y, int z, float dx, float dy,
-                                           float dz, float out[3]) {
-  int x0, y0, z0;
-  float fx, fy, fz;
-  cell(x, dx, x0, fx);
-  cell(y, dy, y0, fy);
-  cell(z, dz, z0, fz);
-  float w[2][2][2];
-  long long off[2][2][2];
-  bool ok[2][2][2];
-#pragma unroll
-  for (int k = 0; k < 2; ++k)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        int xi = x0 + i, yi = y0 + j, zi = z0 + k;
-        ok[k][j][i] = (unsigned)xi < (unsigned)g.nx && (unsigned)yi < (unsigned)g.ny &&
-                      (unsigned)zi < (unsigned)g.nz;
-        off[k][j][i] = ((long long)zi * g.ny + yi) * g.nx + xi;
-        w[k][j][i] = (i ? fx : 1.0f - fx) * (j ? fy : 1.0f - fy) * (k ? fz : 1.0f - fz);
-      }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const float* Uc = U + c * g.N;
-    float s = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-          s += ok[k][j][i] ? w[k][j][i] * Uc[off[k][j][i]] : 0.0f;
-    out[c] = s;
-  }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBX* kBY)
     k_warp(const T* __restrict__ M, const float* __restrict__ u, Geom g,
            float* __restrict__ Mw, float* __restrict__ dMw) {
-  int x, y, z;
-  long long i;
+  int x, y, z, i;
   if (!voxel(g, x, y, z, i)) return;
-  float d[3];
-  float v = trilinear(M, g, x, y, z, u[i], u[g.N + i], u[2 * g.N + i],
-                      dMw ? d : nullptr);
-  Mw[i] = v;
+  const int N = static_cast<int>(g.N);
+  const RBuf bm = make_rbuf_n(M, N);
+  const BCell c = make_bcell(g, x, y, z, u[i], u[N + i], u[2 * N + i]);
+  float v[8], d[3];
+  bcorners<T>(bm, g, c, v);
+  Mw[i] = binterp(c, v, dMw ? d : nullptr);
   if (dMw) {
     dMw[i] = d[0];
-    dMw[g.N + i] = d[1];
-    dMw[2 * g.N + i] = d[2];
+    dMw[N + i] = d[1];
+    dMw[2 * N + i] = d[2];
   }
 }
 
@@ -94,7 +55,7 @@ __global__ void __launch_bounds__(kBX* kBY)
   float r, lam;
   if (st) {
     if (st->stalled) return;
-    int cur = st->cur;
+    const int cur = st->cur;
     uin = cur ? U1 : U0;
     uo = cur ? U0 : U1;
     r = static_cast<float>(st->r);
@@ -105,25 +66,37 @@ __global__ void __launch_bounds__(kBX* kBY)
     r = r_arg;
     lam = lam_arg;
   }
-  int x, y, z;
-  long long i;
+  int x, y, z, i;
   if (!voxel(g, x, y, z, i)) return;
-  float g0 = G[i], g1 = G[g.N + i], g2 = G[2 * g.N + i];
-  float s = -r / (g0 * g0 + g1 * g1 + g2 * g2 + lam);
-  float e0 = eps * (s * g0), e1 = eps * (s * g1), e2 = eps * (s * g2);
-  float b[3];
+  const int N = static_cast<int>(g.N);
+  const float g0 = G[i], g1 = G[N + i], g2 = G[2 * N + i];
+  const float s = -r / (g0 * g0 + g1 * g1 + g2 * g2 + lam);
+  const float e0 = eps * (s * g0), e1 = eps * (s * g1), e2 = eps * (s * g2);
+  float b0, b1, b2;
   if (compositive) {
-    trilinear3(uin, g, x, y, z, e0, e1, e2, b);
+    const BCell c = make_bcell(g, x, y, z, e0, e1, e2);
+    float v[8];
+    bcorners<float>(make_rbuf_n(uin, N), g, c, v);
+    b0 = binterp(c, v, nullptr);
+    bcorners<float>(make_rbuf_n(uin + N, N), g, c, v);
+    b1 = binterp(c, v, nullptr);
+    bcorners<float>(make_rbuf_n(uin + 2 * N, N), g, c, v);
+    b2 = binterp(c, v, nullptr);
   } else {
-    b[0] = uin[i];
-    b[1] = uin[g.N + i];
-    b[2] = uin[2 * g.N + i];
+    b0 = uin[i];
+    b1 = uin[N + i];
+    b2 = uin[2 * N + i];
   }
-  float n0 = e0 + b[0], n1 = e1 + b[1], n2 = e2 + b[2];
+  const float n0 = e0 + b0, n1 = e1 + b1, n2 = e2 + b2;
   uo[i] = n0;
-  uo[g.N + i] = n1;
-  uo[2 * g.N + i] = n2;
-  if (M) Mw[i] = trilinear(M, g, x, y, z, n0, n1, n2, nullptr);
+  uo[N + i] = n1;
+  uo[2 * N + i] = n2;
+  if (M) {
+    const BCell c = make_bcell(g, x, y, z, n0, n1, n2);
+    float v[8];
+    bcorners<T>(make_rbuf_n(M, N), g, c, v);
+    Mw[i] = binterp(c, v, nullptr);
+  }
 }
 
 __device__ __forceinline__ double clampd(double v, double lo, double hi) {

@@ -38,60 +38,200 @@ struct Geom {
 };
 
 // ---------------------------------------------------------------- helpers
-__device__ __forceinline__ float ldf(const float* p, long long i) { return p[i]; }
-__device__ __forceinline__ float ldf(const uint16_t* p, long long i) {
+// Voxel counts are below 2^31 (checked at context creation), so indices
+// within one channel are 32-bit.
+__device__ __forceinline__ float ldf(const float* p, int i) { return p[i]; }
+__device__ __forceinline__ float ldf(const uint16_t* p, int i) {
   return __uint_as_float(static_cast<uint32_t>(p[i]) << 16);
 }
 
 // Integer cell and fractional offset of the sample coordinate base + d.
 // base + d is formed in FP64, which is exact for an FP32 d and an integer
 // base, so the choice of cell does not depend on the rounding of a float sum.
+// Coordinates beyond +-1e9 (and NaN) are clamped far outside the volume.
 __device__ __forceinline__ void cell(int base, float d, int& i0, float& f) {
   double p = static_cast<double>(base) + static_cast<double>(d);
+  p = fmin(fmax(p, -1e9), 1e9);
   double fl = floor(p);
   i0 = static_cast<int>(fl);
   f = static_cast<float>(p - fl);
 }
 
-// Trilinear sample of V at (x+dx, y+dy, z+dz) with zero padding; when grad
-// is non-null it receives the derivative of the interpolant on the cell.
-template <typename T>
-__device__ __forceinline__ float trilinear(const T* __restrict__ V, const Geom g,
-                                           int x, int y, int z, float dx, float dy,
-                                           float dz, float* grad) {
+// The trilinear cell of the point (x+dx, y+dy, z+dz): lower corner, weights
+// and whether all eight corners lie inside the volume.
+struct Cell {
   int x0, y0, z0;
   float fx, fy, fz;
-  cell(x, dx, x0, fx);
-  cell(y, dy, y0, fy);
-  cell(z, dz, z0, fz);
-  float c[2][2][2];
+  bool interior;
+  int base;  // linear index of the lower corner (meaningful when interior)
+};
+
+__device__ __forceinline__ Cell make_cell(const Geom& g, int x, int y, int z, float dx,
+                                          float dy, float dz) {
+  Cell c;
+  cell(x, dx, c.x0, c.fx);
+  cell(y, dy, c.y0, c.fy);
+  cell(z, dz, c.z0, c.fz);
+  c.interior = (unsigned)c.x0 < (unsigned)(g.nx - 1) &&
+               (unsigned)c.y0 < (unsigned)(g.ny - 1) &&
+               (unsigned)c.z0 < (unsigned)(g.nz - 1);
+  c.base = c.interior ? (c.z0 * g.ny + c.y0) * g.nx + c.x0 : 0;
+  return c;
+}
+
+// The eight corner values v[4k + 2j + i] (i along x, j along y, k along z);
+// corners outside the volume read as 0.
+template <typename T>
+__device__ __forceinline__ void corners(const T* __restrict__ V, const Geom& g,
+                                        const Cell& c, float v[8]) {
+  if (c.interior) {
+    const int b = c.base, sy = g.nx, sz = g.nx * g.ny;
+    v[0] = ldf(V, b);
+    v[1] = ldf(V, b + 1);
+    v[2] = ldf(V, b + sy);
+    v[3] = ldf(V, b + sy + 1);
+    v[4] = ldf(V, b + sz);
+    v[5] = ldf(V, b + sz + 1);
+    v[6] = ldf(V, b + sz + sy);
+    v[7] = ldf(V, b + sz + sy + 1);
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < 2; ++k)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        int xi = x0 + i, yi = y0 + j, zi = z0 + k;
-        bool in = (unsigned)xi < (unsigned)g.nx && (unsigned)yi < (unsigned)g.ny &&
-                  (unsigned)zi < (unsigned)g.nz;
-        c[k][j][i] = in ? ldf(V, ((long long)zi * g.ny + yi) * g.nx + xi) : 0.0f;
+        const int xi = c.x0 + i, yi = c.y0 + j, zi = c.z0 + k;
+        const bool in = (unsigned)xi < (unsigned)g.nx && (unsigned)yi < (unsigned)g.ny &&
+                        (unsigned)zi < (unsigned)g.nz;
+        v[4 * k + 2 * j + i] = in ? ldf(V, (zi * g.ny + yi) * g.nx + xi) : 0.0f;
       }
-  float gx0 = 1.0f - fx, gy0 = 1.0f - fy, gz0 = 1.0f - fz;
-  // interpolate along x first
-  float c00 = gx0 * c[0][0][0] + fx * c[0][0][1];
-  float c01 = gx0 * c[0][1][0] + fx * c[0][1][1];
-  float c10 = gx0 * c[1][0][0] + fx * c[1][0][1];
-  float c11 = gx0 * c[1][1][0] + fx * c[1][1][1];
-  float c0 = gy0 * c00 + fy * c01;
-  float c1 = gy0 * c10 + fy * c11;
+}
+
+// Interpolated value from the corners; grad (may be null) receives the
+// derivative of the interpolant on the cell.
+__device__ __forceinline__ float interp(const Cell& c, const float v[8], float* grad) {
+  const float gx0 = 1.0f - c.fx, gy0 = 1.0f - c.fy, gz0 = 1.0f - c.fz;
+  const float c00 = gx0 * v[0] + c.fx * v[1];
+  const float c01 = gx0 * v[2] + c.fx * v[3];
+  const float c10 = gx0 * v[4] + c.fx * v[5];
+  const float c11 = gx0 * v[6] + c.fx * v[7];
+  const float c0 = gy0 * c00 + c.fy * c01;
+  const float c1 = gy0 * c10 + c.fy * c11;
   if (grad) {
-    float d00 = c[0][0][1] - c[0][0][0], d01 = c[0][1][1] - c[0][1][0];
-    float d10 = c[1][0][1] - c[1][0][0], d11 = c[1][1][1] - c[1][1][0];
-    grad[0] = gz0 * (gy0 * d00 + fy * d01) + fz * (gy0 * d10 + fy * d11);
-    grad[1] = gz0 * (c01 - c00) + fz * (c11 - c10);
+    const float d00 = v[1] - v[0], d01 = v[3] - v[2];
+    const float d10 = v[5] - v[4], d11 = v[7] - v[6];
+    grad[0] = gz0 * (gy0 * d00 + c.fy * d01) + c.fz * (gy0 * d10 + c.fy * d11);
+    grad[1] = gz0 * (c01 - c00) + c.fz * (c11 - c10);
     grad[2] = c1 - c0;
   }
-  return gz0 * c0 + fz * c1;
+  return gz0 * c0 + c.fz * c1;
+}
+
+// Trilinear sample of V at (x+dx, y+dy, z+dz) with zero padding.
+template <typename T>
+__device__ __forceinline__ float trilinear(const T* __restrict__ V, const Geom& g,
+                                           int x, int y, int z, float dx, float dy,
+                                           float dz, float* grad) {
+  const Cell c = make_cell(g, x, y, z, dx, dy, dz);
+  float v[8];
+  corners(V, g, c, v);
+  return interp(c, v, grad);
+}
+
+// ------------------------------------------------------- buffer resources
+// A buffer resource addresses one channel with a 32-bit byte offset; the
+// hardware checks the offset against the channel size and returns 0 for any
+// read beyond it (a write beyond it is dropped), so out-of-volume reads need
+// no branch and can never fault.  Channels hold fewer than 2^30 voxels.
+constexpr int kBufDword3 = 0x00020000;  // raw 32-bit access on gfx9-class GPUs
+constexpr unsigned kFarOffset = 0xFFFFFFF0u;  // always beyond num_records
+
+struct RBuf {
+  __amdgpu_buffer_rsrc_t r;
+};
+
+__device__ __forceinline__ RBuf make_rbuf(const void* p, unsigned bytes) {
+  return RBuf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
+                                                (int)bytes, kBufDword3)};
+}
+template <typename T>
+__device__ __forceinline__ RBuf make_rbuf_n(const T* p, int n) {
+  return make_rbuf(p, static_cast<unsigned>(n) * sizeof(T));
+}
+
+// element i of a buffer holding T (float or BF16 bits), as float
+__device__ __forceinline__ float bload(const RBuf& b, unsigned i, float) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(b.r, i * 4u, 0, 0));
+}
+__device__ __forceinline__ float bload(const RBuf& b, unsigned i, uint16_t) {
+  const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(b.r, i * 2u, 0, 0);
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+template <typename T>
+__device__ __forceinline__ float bld(const RBuf& b, unsigned i) {
+  return bload(b, i, T());
+}
+// byte-offset form: o is already a byte offset (kFarOffset reads 0)
+__device__ __forceinline__ float bld_off(const RBuf& b, unsigned o, float) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(b.r, o, 0, 0));
+}
+__device__ __forceinline__ void bst(const RBuf& b, unsigned i, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), b.r, i * 4u, 0, 0);
+}
+
+// The trilinear cell addressed through buffers: the eight corner offsets are
+// formed in 32-bit arithmetic and every corner is loaded unconditionally; a
+// corner outside the volume along any axis is then replaced by 0.
+struct BCell {
+  float fx, fy, fz;
+  unsigned base;           // linear index of the lower corner (wraps if outside)
+  unsigned char m;         // bit 4k+2j+i: corner (i, j, k) inside the volume
+};
+
+__device__ __forceinline__ BCell make_bcell(const Geom& g, int x, int y, int z, float dx,
+                                            float dy, float dz) {
+  int x0, y0, z0;
+  BCell c;
+  cell(x, dx, x0, c.fx);
+  cell(y, dy, y0, c.fy);
+  cell(z, dz, z0, c.fz);
+  const unsigned ux = (unsigned)x0, uy = (unsigned)y0, uz = (unsigned)z0;
+  const bool x0i = ux < (unsigned)g.nx, x1i = ux + 1u < (unsigned)g.nx;
+  const bool y0i = uy < (unsigned)g.ny, y1i = uy + 1u < (unsigned)g.ny;
+  const bool z0i = uz < (unsigned)g.nz, z1i = uz + 1u < (unsigned)g.nz;
+  c.m = 0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        if ((i ? x1i : x0i) && (j ? y1i : y0i) && (k ? z1i : z0i)) c.m |= 1u << (4 * k + 2 * j + i);
+  c.base = (uz * (unsigned)g.ny + uy) * (unsigned)g.nx + ux;
+  return c;
+}
+
+template <typename T>
+__device__ __forceinline__ void bcorners(const RBuf& b, const Geom& g, const BCell& c,
+                                         float v[8]) {
+  const unsigned sy = (unsigned)g.nx, sz = (unsigned)g.nx * (unsigned)g.ny;
+  const unsigned o[8] = {c.base,      c.base + 1,      c.base + sy,      c.base + sy + 1,
+                         c.base + sz, c.base + sz + 1, c.base + sz + sy, c.base + sz + sy + 1};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const float t = bld<T>(b, o[q]);
+    v[q] = (c.m >> q) & 1u ? t : 0.0f;
+  }
+}
+
+__device__ __forceinline__ float binterp(const BCell& b, const float v[8], float* grad) {
+  Cell c;
+  c.fx = b.fx;
+  c.fy = b.fy;
+  c.fz = b.fz;
+  return interp(c, v, grad);
 }
 
 // Bijective remap of a linear block index so that the blocks which the
@@ -148,6 +288,10 @@ hipError_t launch_bwd(const void* F, const void* M, lmr_dtype t, const float* Mw
 // P5: Gaussian smoothing of the raw gradient.
 hipError_t launch_smooth(const float* graw, const Geom& g, const lmr_params& p,
                          const DevState* st, float* out, hipStream_t s);
+hipError_t launch_avgpool(const void* in, lmr_dtype t, int nz, int ny, int nx, int f,
+                          float* out, hipStream_t s);
+hipError_t launch_upsample_field(const float* uc, int nzc, int nyc, int nxc, float* uf,
+                                 hipStream_t s);
 // Overwrite every field of *st except `cur` with the fields of v.
 hipError_t launch_set_state(DevState* st, const DevState& v, hipStream_t s);
 // dst[0..n) = v (a kernel, so that graph captures hold no memset node).

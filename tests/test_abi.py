@@ -52,7 +52,7 @@ def test_default_params_and_errors_without_device():
         assert L.lmr_create(C.byref(h), 8, 8, 8, 0, C.byref(pb), None) == 1, bad
     assert L.lmr_create(C.byref(h), 0, 8, 8, 0, C.byref(p), None) == 1
     assert L.lmr_create(C.byref(h), 8, 8, 8, 5, C.byref(p), None) == 1
-    assert L.lmr_create(C.byref(h), 2048, 2048, 1024, 0, C.byref(p), None) == 1
+    assert L.lmr_create(C.byref(h), 1024, 1024, 1024, 0, C.byref(p), None) == 1
     assert L.lmr_strerror(0) == b"ok"
     assert L.lmr_step(None, None, None, 1) == 1
 

@@ -1,0 +1,62 @@
+"""GPU parity of the coarse-to-fine pyramid against the FP64 oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_2603_19371_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda().to(dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("img", ["f32", "bf16"])
+@pytest.mark.parametrize("f", [2, 4])
+def test_avgpool_matches_oracle(L, orc, img, f):
+    from paper_2603_19371_amd.phantoms import bf16_to_f32, to_bf16_rne
+    a = np.random.default_rng(1).uniform(0, 1, (24, 40, 72)).astype(np.float32)
+    if img == "bf16":
+        a = bf16_to_f32(to_bf16_rne(a))
+    got = host(L.avgpool(dev(a, torch.bfloat16 if img == "bf16" else torch.float32), f))
+    ref = orc.avgpool(a, f)
+    assert np.abs(got - ref).max() < 1e-6
+
+
+def test_upsample_matches_oracle(L, orc):
+    uc = np.random.default_rng(2).standard_normal((3, 7, 13, 21)).astype(np.float32)
+    got = host(L.upsample_field(dev(uc)))
+    ref = orc.upsample_field(uc, (14, 26, 42))
+    assert np.abs(got - ref).max() < 2e-6
+
+
+def test_pyramid_run_with_oracle_decisions(L, orc):
+    """A short 3-level registration (factors 4/2/1) with the oracle's
+    decisions replayed: final field within 1e-4 voxel."""
+    from paper_2603_19371_amd import phantoms
+    ph = phantoms.brain((32, 40, 48), seed=3)
+    levels = [(4, 4), (2, 3), (1, 2)]
+    p = orc.Params(window=5)
+    u_ref, dec = orc.register(ph.F, ph.M, p, levels, lambda0=1.0)
+    flat = [int(d) for lv in dec for d in lv]
+    pyr = L.Pyramid(ph.F.shape, (4, 2, 1), window=5)
+    out = pyr.run(dev(ph.F), dev(ph.M), [n for _, n in levels], lambda0=1.0,
+                  decisions=flat)
+    err = np.abs(host(out) - u_ref).max()
+    print(f"[pyramid] max|err|={err:.3e}", flush=True)
+    assert err < 1e-4, err
+    for l, (_, n) in enumerate(levels):
+        assert pyr.level(l).state()["attempts"] == n
