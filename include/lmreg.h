@@ -168,6 +168,16 @@ lmr_status lmr_loss_grad(lmr_ctx* ctx, const void* fixed, const void* moving,
 lmr_status lmr_update(lmr_ctx* ctx, const float* u, const float* g_smooth,
                       double r, double lambda, float* u_out);
 
+/* Folded-voxel count: the number of voxels where det(I + grad u) <= 0, with
+ * central differences inside the volume and first-order one-sided differences
+ * on its faces (the folding test that judges a deformation; used by the
+ * learned initializer's gate).  u: device field, or NULL for the context's
+ * accepted field (then the raw-gradient workspace is overwritten).  det_out
+ * (device [nz][ny][nx], may be NULL) receives det(I + grad u) rounded to
+ * FP32; the decision is taken in FP64.  Synchronises. */
+lmr_status lmr_folded_count(lmr_ctx* ctx, const float* u, long long* count_out,
+                            float* det_out);
+
 /* Gaussian smoothing of a field (step 5 alone): out = G_sigma * g with the
  * context's grad_sigma, taps k in [-R, R], R = ceil(3 sigma), zero padding
  * (Eulerian descent, Sec. 2.1).  g and out: device [3][nz][ny][nx], distinct. */
@@ -224,6 +234,49 @@ lmr_status lmr_pyramid_run(lmr_pyramid* pyr, const void* fixed, const void* movi
 /* The context of level l (borrowed; valid until lmr_pyramid_destroy). */
 lmr_ctx* lmr_pyramid_level(lmr_pyramid* pyr, int level);
 void lmr_pyramid_destroy(lmr_pyramid* pyr);
+
+/* ------------------------------------------------------------------------ */
+/* Batched form: npairs pairs of uneven shapes (shapes: host array of npairs
+ * triples nz, ny, nx) advance together, each with its own lambda, loss
+ * history and decision.  One step is ONE persistent launch: a grid of as many
+ * blocks as fit on the GPU at once sweeps the work of all pairs phase by phase
+ * (update, LNCC forward, decision, LNCC backward, smoothing) with a grid
+ * barrier between phases.  The launches of lmr_batch_step are captured in a
+ * HIP graph on first use and replayed.  The batch owns a non-blocking stream;
+ * results of one pair are read through lmr_batch_pair (borrowed context).
+ * Box side 3..9 and Gaussian radius ceil(3 sigma) <= 4 are supported (else
+ * LMR_EINVAL).  A barrier wait longer than 0.25 s (which means the blocks
+ * were not all resident) makes every block leave; lmr_batch_sync reports it
+ * as LMR_EHIP. */
+typedef struct lmr_batch lmr_batch;
+lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes,
+                            lmr_dtype img, const lmr_params* p);
+/* Starts every pair from the identity with lambda0[i] (NULL: 1.0).  fixed[i],
+ * moving[i]: device images of pair i, which must stay valid while the batch
+ * steps (the persistent kernel reads them through a device table). */
+lmr_status lmr_batch_begin(lmr_batch* b, const void* const* fixed,
+                           const void* const* moving, const double* lambda0);
+/* Enqueues n_iters iterations (one persistent launch each); use_graph = 1
+ * replays a captured HIP graph of the n_iters launches. */
+lmr_status lmr_batch_step(lmr_batch* b, int n_iters, int use_graph);
+/* Synchronises the batch stream; LMR_EHIP if a barrier wait timed out. */
+lmr_status lmr_batch_sync(lmr_batch* b);
+lmr_ctx* lmr_batch_pair(lmr_batch* b, int i);
+/* Tiling knobs: target tile count per pair, minimum z-chunk, persistent
+ * blocks per CU (0 = as many as fit). */
+lmr_status lmr_batch_set_config(lmr_batch* b, int target_tiles, int min_cz,
+                                int blocks_per_cu);
+lmr_status lmr_batch_get_config(lmr_batch* b, int cfg[3]);
+/* Autotuner: times iters_per_trial iterations for every candidate
+ * configuration on the given images and keeps the fastest; with cache_path
+ * the choice is read from / appended to that text file, keyed by the GPU,
+ * image type, window, sigma and the pair shapes.  best_ms (may be NULL)
+ * receives the time of one iteration.  The trials overwrite the pair states:
+ * call lmr_batch_begin afterwards. */
+lmr_status lmr_batch_tune(lmr_batch* b, const void* const* fixed,
+                          const void* const* moving, const char* cache_path,
+                          int iters_per_trial, double* best_ms);
+void lmr_batch_destroy(lmr_batch* b);
 
 /* Average pooling by f (every dimension divisible by f): out (device, FP32,
  * [nz/f][ny/f][nx/f]) is the mean of each f^3 block of img. */

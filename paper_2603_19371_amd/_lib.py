@@ -103,6 +103,7 @@ def lib() -> C.CDLL:
                                       C.POINTER(PairState)]),
             "lmr_smooth": (_I, [_V, _V, _V]),
             "lmr_set_state": (_I, [_V, C.POINTER(PairState)]),
+            "lmr_folded_count": (_I, [_V, _V, C.POINTER(_LL), _V]),
             "lmr_kernel_name": (C.c_char_p, [_I]),
             "lmr_profile_start": (_I, [_V, _I, _I]),
             "lmr_profile_stop": (_I, [_V, C.POINTER(KernelTime)]),
@@ -114,6 +115,29 @@ def lib() -> C.CDLL:
                                      _V]),
             "lmr_pyramid_level": (_V, [_V, _I]),
             "lmr_pyramid_destroy": (None, [_V]),
+            "lmr_batch_create": (_I, [C.POINTER(_V), _I, C.POINTER(_I), _I,
+                                      C.POINTER(Params)]),
+            "lmr_batch_begin": (_I, [_V, C.POINTER(_V), C.POINTER(_V),
+                                     C.POINTER(_D)]),
+            "lmr_batch_step": (_I, [_V, _I, _I]),
+            "lmr_batch_sync": (_I, [_V]),
+            "lmr_batch_pair": (_V, [_V, _I]),
+            "lmr_batch_set_config": (_I, [_V, _I, _I, _I]),
+            "lmr_batch_get_config": (_I, [_V, C.POINTER(_I)]),
+            "lmr_batch_tune": (_I, [_V, C.POINTER(_V), C.POINTER(_V), C.c_char_p,
+                                    _I, C.POINTER(_D)]),
+            "lmr_batch_destroy": (None, [_V]),
+            "lmr_unet_param_count": (C.c_int64, []),
+            "lmr_unet_layer_info": (_I, [_I, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I),
+                                         C.POINTER(C.c_int64)]),
+            "lmr_unet_create": (_I, [C.POINTER(_V), _I, _I, _I, _V]),
+            "lmr_unet_destroy": (None, [_V]),
+            "lmr_unet_set_params": (_I, [_V, _V]),
+            "lmr_unet_get_params": (_I, [_V, _V]),
+            "lmr_unet_get_grads": (_I, [_V, _V]),
+            "lmr_unet_forward": (_I, [_V, _V, _V, _I, _I, _V]),
+            "lmr_unet_backward": (_I, [_V, _V, _D, _I, _V]),
+            "lmr_unet_adam": (_I, [_V, _D, _D, _D, _D, _D]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -133,7 +157,13 @@ def exported_symbols():
             "lmr_set_state", "lmr_kernel_name", "lmr_profile_start",
             "lmr_profile_stop", "lmr_avgpool", "lmr_upsample_field",
             "lmr_pyramid_create", "lmr_pyramid_run", "lmr_pyramid_level",
-            "lmr_pyramid_destroy"]
+            "lmr_pyramid_destroy", "lmr_folded_count", "lmr_batch_create",
+            "lmr_batch_begin", "lmr_batch_step", "lmr_batch_sync", "lmr_batch_pair",
+            "lmr_batch_set_config", "lmr_batch_get_config", "lmr_batch_tune",
+            "lmr_batch_destroy", "lmr_unet_param_count", "lmr_unet_layer_info",
+            "lmr_unet_create", "lmr_unet_destroy", "lmr_unet_set_params",
+            "lmr_unet_get_params", "lmr_unet_get_grads", "lmr_unet_forward",
+            "lmr_unet_backward", "lmr_unet_adam"]
 
 
 def _check(status: int, what: str):
@@ -236,6 +266,16 @@ class Context:
 
     def profile_stop(self) -> dict:
         return _profile_stop(self._h)
+
+    def folded_count(self, u=None, with_det=False):
+        """Voxels with det(I + grad u) <= 0 (u None: the accepted field)."""
+        up = self._field(u, "u") if u is not None else None
+        det = torch.empty(self.shape, device="cuda") if with_det else None
+        n = C.c_longlong()
+        _check(lib().lmr_folded_count(self._h, up, C.byref(n),
+                                      det.data_ptr() if with_det else None),
+               "lmr_folded_count")
+        return (n.value, det) if with_det else n.value
 
     def set_state(self, state: dict):
         s = PairState(**{k: state.get(k, 0) for k, _ in PairState._fields_})
@@ -375,6 +415,85 @@ class Pyramid:
         return out
 
 
+class Batch:
+    """Uneven-size pairs advanced together by one persistent launch per
+    iteration (lmr_batch).  The batch owns its stream; every call that reads
+    results synchronises it."""
+
+    def __init__(self, shapes, img_dtype=torch.float32, params: Params | None = None,
+                 **kw):
+        self.shapes = [tuple(int(s) for s in sh) for sh in shapes]
+        self.img_dtype = img_dtype
+        self.params = params if params is not None else Params.make(**kw)
+        self._h = _V()
+        flat = (C.c_int * (3 * len(self.shapes)))(*[s for sh in self.shapes for s in sh])
+        code = LMR_BF16 if img_dtype == torch.bfloat16 else LMR_F32
+        _check(lib().lmr_batch_create(C.byref(self._h), len(self.shapes), flat, code,
+                                      C.byref(self.params)), "lmr_batch_create")
+        self._keep = None
+
+    def close(self):
+        if self._h:
+            lib().lmr_batch_destroy(self._h)
+            self._h = _V()
+
+    __del__ = close
+
+    def _ptrs(self, Fs, Ms):
+        if len(Fs) != len(self.shapes) or len(Ms) != len(self.shapes):
+            raise LmrError("one fixed and one moving image per pair")
+        fp = (C.c_void_p * len(Fs))(*[_dev(F, sh, self.img_dtype, "fixed")
+                                      for F, sh in zip(Fs, self.shapes)])
+        mp = (C.c_void_p * len(Ms))(*[_dev(M, sh, self.img_dtype, "moving")
+                                      for M, sh in zip(Ms, self.shapes)])
+        return fp, mp
+
+    def begin(self, Fs, Ms, lambda0=None):
+        fp, mp = self._ptrs(Fs, Ms)
+        lp = None if lambda0 is None else (C.c_double * len(Fs))(*lambda0)
+        _check(lib().lmr_batch_begin(self._h, fp, mp, lp), "lmr_batch_begin")
+        self._keep = (list(Fs), list(Ms))   # the device table points at them
+
+    def step(self, n=1, graph=True):
+        _check(lib().lmr_batch_step(self._h, int(n), int(bool(graph))), "lmr_batch_step")
+
+    def sync(self):
+        _check(lib().lmr_batch_sync(self._h), "lmr_batch_sync")
+
+    def tune(self, Fs, Ms, cache_path=None, iters=3):
+        fp, mp = self._ptrs(Fs, Ms)
+        ms = C.c_double()
+        _check(lib().lmr_batch_tune(self._h, fp, mp,
+                                    cache_path.encode() if cache_path else None,
+                                    int(iters), C.byref(ms)), "lmr_batch_tune")
+        return ms.value
+
+    def config(self):
+        cfg = (C.c_int * 3)()
+        _check(lib().lmr_batch_get_config(self._h, cfg), "lmr_batch_get_config")
+        return dict(target_tiles=cfg[0], min_cz=cfg[1], blocks_per_cu=cfg[2])
+
+    def set_config(self, target_tiles, min_cz, blocks_per_cu=0):
+        _check(lib().lmr_batch_set_config(self._h, int(target_tiles), int(min_cz),
+                                          int(blocks_per_cu)), "lmr_batch_set_config")
+
+    def pair(self, i) -> "PairView":
+        h = lib().lmr_batch_pair(self._h, int(i))
+        if not h:
+            raise LmrError(f"no pair {i}")
+        return PairView(C.c_void_p(h), self.shapes[i])
+
+
+class PairView(LevelView):
+    """Borrowed view of one pair of a batch."""
+
+    def field(self):
+        out = torch.empty((3,) + self.shape, device="cuda")
+        _check(lib().lmr_get_field(self._h, out.data_ptr()), "lmr_get_field")
+        _check(lib().lmr_get_state(self._h, C.byref(PairState())), "lmr_get_state")
+        return out
+
+
 def avgpool(img: torch.Tensor, f: int, stream=None) -> torch.Tensor:
     shape = tuple(img.shape)
     if len(shape) != 3 or any(s % f for s in shape):
@@ -395,3 +514,77 @@ def upsample_field(uc: torch.Tensor, stream=None) -> torch.Tensor:
     _check(lib().lmr_upsample_field(p, *shape, out.data_ptr(), _stream_handle(stream)),
            "lmr_upsample_field")
     return out
+
+
+def unet_layers():
+    """(cin, cout, relu, offset) of every U-Net layer (lmreg_unet.h)."""
+    out = []
+    for l in range(15):
+        ci, co, re, off = C.c_int(), C.c_int(), C.c_int(), C.c_int64()
+        _check(lib().lmr_unet_layer_info(l, C.byref(ci), C.byref(co), C.byref(re),
+                                         C.byref(off)), "lmr_unet_layer_info")
+        out.append((ci.value, co.value, bool(re.value), off.value))
+    return out
+
+
+def unet_param_count() -> int:
+    return int(lib().lmr_unet_param_count())
+
+
+class UNet:
+    """The learned initializer's network (lmr_unet) at a fixed resolution."""
+
+    def __init__(self, shape, stream=None):
+        self.shape = tuple(int(s) for s in shape)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.n_params = unet_param_count()
+        self._h = _V()
+        _check(lib().lmr_unet_create(C.byref(self._h), *self.shape,
+                                     _stream_handle(self.stream)), "lmr_unet_create")
+
+    def close(self):
+        if self._h:
+            lib().lmr_unet_destroy(self._h)
+            self._h = _V()
+
+    __del__ = close
+
+    def set_params(self, flat: torch.Tensor):
+        _check(lib().lmr_unet_set_params(
+            self._h, _dev(flat, (self.n_params,), torch.float32, "params")),
+            "lmr_unet_set_params")
+
+    def params(self) -> torch.Tensor:
+        out = torch.empty(self.n_params, device="cuda")
+        _check(lib().lmr_unet_get_params(self._h, out.data_ptr()), "lmr_unet_get_params")
+        return out
+
+    def grads(self) -> torch.Tensor:
+        out = torch.empty(self.n_params, device="cuda")
+        _check(lib().lmr_unet_get_grads(self._h, out.data_ptr()), "lmr_unet_get_grads")
+        return out
+
+    def forward(self, F, M, pool=False, out=None):
+        """Predicted field [3][nz][ny][nx] (FP32) from images of the network's
+        size, or of twice its size with pool=True."""
+        ish = tuple(2 * s for s in self.shape) if pool else self.shape
+        f = _dev(F, ish, F.dtype, "fixed")
+        m = _dev(M, ish, F.dtype, "moving")
+        if out is None:
+            out = torch.empty((3,) + self.shape, device="cuda")
+        _check(lib().lmr_unet_forward(self._h, f, m, _img_code(F), int(bool(pool)),
+                                      _dev(out, (3,) + self.shape, torch.float32, "out")),
+               "lmr_unet_forward")
+        return out
+
+    def backward(self, target, target_scale=1.0, accumulate=False, loss=None):
+        """MSE backward against target_scale * target; `loss` (a float64 CUDA
+        tensor of one element) receives the MSE without synchronising."""
+        lp = _dev(loss, (1,), torch.float64, "loss") if loss is not None else None
+        _check(lib().lmr_unet_backward(
+            self._h, _dev(target, (3,) + self.shape, torch.float32, "target"),
+            float(target_scale), int(bool(accumulate)), lp), "lmr_unet_backward")
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=1.0):
+        _check(lib().lmr_unet_adam(self._h, float(lr), float(beta1), float(beta2),
+                                   float(eps), float(grad_scale)), "lmr_unet_adam")

@@ -4,7 +4,11 @@
 
 Every source under csrc/ is compiled by hipcc into an object, in parallel,
 and the objects are linked into paper_2603_19371_amd/liblmreg.so.  Packed
-FP32 instructions are disabled for all device code.
+FP32 instructions are disabled for all device code.  Floating-point
+contraction is off: every fused multiply-add is written out in the source, so
+a device function inlined into different kernels rounds identically in each
+(the batched kernel reproduces the per-pair kernels bit for bit, and a run
+resumed from a checkpoint reproduces the uninterrupted one).
 """
 from __future__ import annotations
 
@@ -34,6 +38,7 @@ def _hipcc() -> str:
 def _flags():
     return ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-ffp-contract=off",
             "-Wno-unused-command-line-argument", "-Wno-unknown-warning-option",
             "-I", INCLUDE, "-I", CSRC]
 

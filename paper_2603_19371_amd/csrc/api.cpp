@@ -8,58 +8,23 @@
 #include <new>
 #include <vector>
 
+#include "ctx.h"
 #include "lmr_internal.h"
 
 using namespace lmr;
-
-// Event pairs recorded around the kernels of sampled attempts.
-struct Profiler {
-  bool on = false;
-  int stride = 1;
-  int max_attempts = 0;
-  int recorded = 0;   // attempts recorded
-  long long seen = 0; // attempts enqueued while on
-  std::vector<hipEvent_t> ev;  // 2 * LMR_NUM_KERNELS per recorded attempt
-};
-
-struct lmr_ctx {
-  Profiler prof;
-  Geom g;
-  lmr_dtype img;
-  lmr_params p;
-  DecideParams dp;
-  hipStream_t stream;
-  void* arena;
-  float* U[2];
-  float* G;
-  float* graw;
-  float* maps;
-  float* Mw;
-  double* partials;
-  int nparts;
-  DevState* st;
-  double* probe;
-  DevState* st_probe;
-  double* part_probe;
-  bool begun;
-};
 
 namespace {
 
 thread_local char g_err[256] = "";
 
-lmr_status hip_fail(hipError_t e) {
+}  // namespace
+
+lmr_status lmr::hip_fail(hipError_t e) {
   snprintf(g_err, sizeof g_err, "%s", hipGetErrorString(e));
   return LMR_EHIP;
 }
 
-#define LMR_HIP(expr)                         \
-  do {                                        \
-    hipError_t e_ = (expr);                   \
-    if (e_ != hipSuccess) return hip_fail(e_); \
-  } while (0)
-
-bool params_ok(const lmr_params* p) {
+bool lmr::params_ok(const lmr_params* p) {
   if (!p) return false;
   if (p->window < 3 || p->window > 9 || (p->window % 2) == 0) return false;
   if (!(p->grad_sigma >= 0.0 && p->grad_sigma <= 2.0)) return false;
@@ -71,6 +36,8 @@ bool params_ok(const lmr_params* p) {
   if (p->max_retries < 1) return false;
   return true;
 }
+
+namespace {
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
@@ -180,7 +147,8 @@ lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
                           align256(sizeof(DevState)),
                           align256(sizeof(double)),
                           align256(sizeof(DevState)),
-                          align256(sizeof(double))};
+                          align256(sizeof(double)),
+                          align256(sizeof(unsigned long long))};
   size_t total = 0;
   for (size_t s : sizes) total += s;
   hipError_t e = hipMalloc(&c->arena, total);
@@ -200,7 +168,8 @@ lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
   c->st = reinterpret_cast<DevState*>(q); q += sizes[7];
   c->probe = reinterpret_cast<double*>(q); q += sizes[8];
   c->st_probe = reinterpret_cast<DevState*>(q); q += sizes[9];
-  c->part_probe = reinterpret_cast<double*>(q);
+  c->part_probe = reinterpret_cast<double*>(q); q += sizes[10];
+  c->counter = reinterpret_cast<unsigned long long*>(q);
   c->begun = false;
   *out = c;
   return LMR_OK;
@@ -337,6 +306,23 @@ lmr_status lmr_update(lmr_ctx* c, const float* u, const float* g_smooth, double 
   if (!c || !u || !g_smooth || !u_out || u == u_out) return LMR_EINVAL;
   LMR_HIP(launch_update(nullptr, LMR_F32, c->g, c->p, nullptr, g_smooth, nullptr,
                         nullptr, u, u_out, r, lambda, c->Mw, c->stream));
+  return LMR_OK;
+}
+
+lmr_status lmr_folded_count(lmr_ctx* c, const float* u, long long* count_out,
+                            float* det_out) {
+  if (!c || !count_out) return LMR_EINVAL;
+  if (!u) {
+    if (!c->begun) return LMR_ESTATE;
+    // the accepted field, copied so that the kernel sees a fixed pointer
+    LMR_HIP(launch_copy_cur(c->st, c->U[0], c->U[1], c->graw, 3 * c->g.N, c->stream));
+    u = c->graw;
+  }
+  LMR_HIP(launch_folds(u, c->g, c->counter, det_out, c->stream));
+  unsigned long long n = 0;
+  LMR_HIP(hipMemcpyAsync(&n, c->counter, sizeof n, hipMemcpyDeviceToHost, c->stream));
+  LMR_HIP(hipStreamSynchronize(c->stream));
+  *count_out = static_cast<long long>(n);
   return LMR_OK;
 }
 

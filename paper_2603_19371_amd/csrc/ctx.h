@@ -1,0 +1,53 @@
+// The context of one registration pair (shared by api.cpp and api_batch.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "lmr_internal.h"
+
+// Event pairs recorded around the kernels of sampled attempts.
+struct Profiler {
+  bool on = false;
+  int stride = 1;
+  int max_attempts = 0;
+  int recorded = 0;   // attempts recorded
+  long long seen = 0; // attempts enqueued while on
+  std::vector<hipEvent_t> ev;  // 2 * LMR_NUM_KERNELS per recorded attempt
+};
+
+struct lmr_ctx {
+  Profiler prof;
+  lmr::Geom g;
+  lmr_dtype img;
+  lmr_params p;
+  lmr::DecideParams dp;
+  hipStream_t stream;
+  void* arena;
+  float* U[2];
+  float* G;
+  float* graw;
+  float* maps;
+  float* Mw;
+  double* partials;
+  int nparts;
+  lmr::DevState* st;
+  double* probe;
+  lmr::DevState* st_probe;
+  double* part_probe;
+  unsigned long long* counter;
+  bool begun;
+};
+
+namespace lmr {
+// Records the text of a failing HIP call for lmr_last_error and returns LMR_EHIP.
+lmr_status hip_fail(hipError_t e);
+bool params_ok(const lmr_params* p);
+}  // namespace lmr
+
+#define LMR_HIP(expr)                                \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return lmr::hip_fail(e_);  \
+  } while (0)

@@ -1,0 +1,96 @@
+// The on-device decision of one LM attempt, as a block-wide device function
+// shared by the per-pair decision kernel and the batched persistent kernel.
+//
+// The cc partial sums are reduced in a fixed order in FP64 into
+// L = -sum cc / N; then (Sec. 2.2, eq. lambda-update; Sec. 3.4,
+// eq. rejection):
+//   reject iff L is not finite, or tau >= 0 and
+//              L - L(t-1) > tau |L(t-1) - L(t-2)|   (reference 0 with < 2 losses)
+//   accept:    lambda <- mu+ lambda if L > L(t-1) else mu- lambda, clamped;
+//              the loss history shifts and the field ping-pong index flips
+//   reject:    lambda <- min(mu+ lambda, lambda_max); after max_retries
+//              consecutive rejections at lambda_max the pair is frozen.
+#pragma once
+
+#include "lmr_internal.h"
+
+namespace lmr {
+
+__device__ __forceinline__ double clamp_d(double v, double lo, double hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// mode 0: attempt (force -1/0/1), mode 1: begin (lambda0), mode 2: probe
+// (*probe = L).  Called by all NT threads of one block; uses NT doubles of LDS.
+template <int NT>
+__device__ void decide_block(DevState* st, const double* __restrict__ partials,
+                             int nparts, long long N, const DecideParams& dp, int mode,
+                             int force, double lambda0, double* probe) {
+  __shared__ double sh[NT];
+  __shared__ int skip;
+  if (threadIdx.x == 0) skip = (mode == 0 && st->stalled) ? 1 : 0;
+  __syncthreads();
+  if (skip) {
+    if (threadIdx.x == 0) st->accepted = 0;
+    __syncthreads();
+    return;
+  }
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += NT) s += partials[k];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double L = -sh[0] / static_cast<double>(N);
+    if (mode == 2) {
+      *probe = L;
+    } else if (mode == 1) {
+      st->lambda = lambda0;
+      st->loss = L;
+      st->loss_prev = L;
+      st->cand_loss = L;
+      st->r = 1.0 + L;
+      st->n_hist = 1;
+      st->retries = 0;
+      st->accepted = 1;
+      st->stalled = 0;
+      st->cur = 0;
+      st->attempts = 0;
+    } else {
+      st->cand_loss = L;
+      st->attempts += 1;
+      int acc;
+      if (force >= 0) {
+        acc = force ? 1 : 0;
+      } else if (!isfinite(L)) {
+        acc = 0;
+      } else if (dp.tau < 0.0) {
+        acc = 1;
+      } else {
+        const double ref = st->n_hist >= 2 ? fabs(st->loss - st->loss_prev) : 0.0;
+        acc = !((L - st->loss) > dp.tau * ref);
+      }
+      if (acc) {
+        const double f = (L > st->loss) ? dp.lambda_inc : dp.lambda_dec;
+        st->lambda = clamp_d(f * st->lambda, dp.lambda_min, dp.lambda_max);
+        st->loss_prev = st->loss;
+        st->loss = L;
+        st->r = 1.0 + L;
+        st->n_hist += 1;
+        st->retries = 0;
+        st->cur = 1 - st->cur;
+      } else {
+        st->lambda = clamp_d(dp.lambda_inc * st->lambda, dp.lambda_min, dp.lambda_max);
+        st->retries += 1;
+        if (st->retries >= dp.max_retries && st->lambda >= dp.lambda_max) st->stalled = 1;
+      }
+      st->accepted = acc;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace lmr

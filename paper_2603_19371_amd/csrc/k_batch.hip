@@ -1,0 +1,216 @@
+// Batched form: every pair of a batch of uneven-size pairs advances by one
+// LM attempt in ONE persistent launch.  The grid holds only as many blocks as
+// fit on the GPU at once (occupancy query); the blocks sweep the work list of
+// each phase and meet at a grid barrier between phases:
+//
+//   P1 update     work items: 256 consecutive voxels of a pair
+//   P2 lncc_fwd   work items: stencil tiles of a pair (partial of cc per tile)
+//   P3 decide     work items: pairs (one block reduces a pair's partials)
+//   P4 lncc_bwd   stencil tiles of the pairs whose candidate was accepted
+//   P5 smooth     stencil tiles of the pairs whose candidate was accepted
+//
+// Each pair keeps its own device state (lambda, loss history, decision), so
+// pairs accept, reject and freeze independently.  A barrier wait is bounded
+// in time: past the limit the kernel records an error and every block leaves
+// (later launches return at once), so a residency mistake cannot hang the
+// device.
+#include "decide.h"
+#include "lmr_batch.h"
+#include "stencil.h"
+#include "update.h"
+
+namespace lmr {
+
+namespace {
+
+constexpr int kTY = 8;
+constexpr int kNT = kTX * kTY;
+
+// Grid-wide barrier among `nblocks` co-resident blocks.  A wait longer than
+// `timeout` ticks of the device's constant-rate wall clock records an error.
+// Returns false when this wait timed out or another block reported one.
+__device__ bool grid_sync(BatchCtl* ctl, unsigned nblocks, unsigned long long timeout) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned g0 = __hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();  // this block's results become visible device-wide
+    const unsigned arrived = atomicAdd(&ctl->count, 1u) + 1u;
+    int good = 1;
+    if (arrived == nblocks) {
+      __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      __hip_atomic_fetch_add(&ctl->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const unsigned long long t0 = wall_clock64();
+      while (__hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ==
+             g0) {
+        if (wall_clock64() - t0 > timeout ||
+            __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          good = 0;
+          atomicExch(&ctl->error, 1);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __threadfence();  // results of the other blocks are visible here
+    ok = good && __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) == 0;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// A state field written earlier in this launch by another block: read with a
+// device-scope atomic so that no cached copy is used.
+__device__ __forceinline__ int fresh(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// pair owning work item `it` of a list whose per-pair offsets are first[p]
+__device__ __forceinline__ int owner(const BatchPair* __restrict__ pairs, int npairs,
+                                     int it, bool tiles) {
+  int p = 0;
+  for (int k = 1; k < npairs; ++k)
+    if ((tiles ? pairs[k].tile0 : pairs[k].vox0) <= it) p = k;
+  return p;
+}
+
+template <int RB, int RG, typename T>
+__global__ void __launch_bounds__(kNT)
+    k_batch_attempt(const BatchPair* __restrict__ pairs, int npairs, int n_vox_items,
+                    int n_tiles, BatchCtl* ctl, DecideParams dp,
+                    unsigned long long timeout) {
+  const int nb = gridDim.x;
+  // after a barrier timeout every later launch returns at once
+  if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+
+  // P1: closed form, compositive integration, candidate warp
+  for (int it = blockIdx.x; it < n_vox_items; it += nb) {
+    const BatchPair& P = pairs[owner(pairs, npairs, it, false)];
+    if (P.st->stalled) continue;
+    const int v = (it - P.vox0) * kNT + threadIdx.x;
+    if (v >= static_cast<int>(P.g.N)) continue;
+    const int x = v % P.g.nx, y = (v / P.g.nx) % P.g.ny, z = v / (P.g.nx * P.g.ny);
+    const UpdateArgs a =
+        update_args_from_state(P.st, P.U0, P.U1, P.G, P.Mw, P.eps, P.compositive);
+    update_voxel(static_cast<const T*>(P.M), P.g, a, x, y, z);
+  }
+  if (!grid_sync(ctl, nb, timeout)) return;
+
+  // P2: LNCC forward, one partial of cc per tile
+  for (int it = blockIdx.x; it < n_tiles; it += nb) {
+    const BatchPair& P = pairs[owner(pairs, npairs, it, true)];
+    if (P.st->stalled) continue;
+    FwdPol<T, kNT> pol;
+    pol.F = static_cast<const T*>(P.F);
+    pol.Mw = P.Mw;
+    pol.maps = P.maps;
+    pol.cc = nullptr;
+    pol.partials = P.partials;
+    pol.N = static_cast<int>(P.g.N);
+    pol.inv_n = P.inv_n;
+    pol.eps = P.cc_eps;
+    const int local = it - P.tile0;
+    int x0, y0, z0;
+    tile_origin(P.t, local, kTY, x0, y0, z0);
+    auto loc = pol.begin_block(P.st);
+    stencil_tile<RB, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc);
+    pol.end_tile(loc, local);
+  }
+  if (!grid_sync(ctl, nb, timeout)) return;
+
+  // P3: per-pair FP64 reduction and decision
+  for (int p = blockIdx.x; p < npairs; p += nb) {
+    const BatchPair& P = pairs[p];
+    decide_block<kNT>(P.st, P.partials, P.t.tiles(), P.g.N, dp, 0, -1, 0.0, nullptr);
+  }
+  if (!grid_sync(ctl, nb, timeout)) return;
+
+  // P4: LNCC and warp backward of the accepted candidates
+  for (int it = blockIdx.x; it < n_tiles; it += nb) {
+    const BatchPair& P = pairs[owner(pairs, npairs, it, true)];
+    if (fresh(&P.st->stalled) || !fresh(&P.st->accepted)) continue;
+    BwdPol<T> pol;
+    pol.F = static_cast<const T*>(P.F);
+    pol.M = static_cast<const T*>(P.M);
+    pol.Mw = P.Mw;
+    pol.maps = P.maps;
+    pol.U0 = P.U0;
+    pol.U1 = P.U1;
+    pol.u_explicit = fresh(&P.st->cur) ? P.U1 : P.U0;  // the accepted candidate
+    pol.graw = P.graw;
+    pol.g = P.g;
+    pol.inv_n = P.inv_n;
+    int x0, y0, z0;
+    tile_origin(P.t, it - P.tile0, kTY, x0, y0, z0);
+    auto loc = pol.begin_block(nullptr);
+    stencil_tile<RB, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc);
+  }
+  if (!grid_sync(ctl, nb, timeout)) return;
+
+  // P5: Gaussian smoothing of the new gradient
+  for (int it = blockIdx.x; it < n_tiles; it += nb) {
+    const BatchPair& P = pairs[owner(pairs, npairs, it, true)];
+    if (fresh(&P.st->stalled) || !fresh(&P.st->accepted)) continue;
+    SmoothPol<RG> pol;
+    pol.in = P.graw;
+    pol.out = P.G;
+    pol.N = static_cast<int>(P.g.N);
+#pragma unroll
+    for (int k = 0; k <= 2 * RG; ++k) pol.w[k] = P.gw[k];
+    int x0, y0, z0;
+    tile_origin(P.t, it - P.tile0, kTY, x0, y0, z0);
+    auto loc = pol.begin_block(P.st);
+    stencil_tile<RG, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc);
+  }
+}
+
+template <int RB, int RG, typename T>
+const void* kernel_ptr() {
+  return reinterpret_cast<const void*>(&k_batch_attempt<RB, RG, T>);
+}
+
+template <typename T>
+const void* kernel_for(int rb, int rg) {
+#define LMR_RG(RBV)                                \
+  switch (rg) {                                    \
+    case 0: return kernel_ptr<RBV, 0, T>();        \
+    case 1: return kernel_ptr<RBV, 1, T>();        \
+    case 2: return kernel_ptr<RBV, 2, T>();        \
+    case 3: return kernel_ptr<RBV, 3, T>();        \
+    case 4: return kernel_ptr<RBV, 4, T>();        \
+    default: return nullptr;                       \
+  }
+  switch (rb) {
+    case 1: LMR_RG(1)
+    case 2: LMR_RG(2)
+    case 3: LMR_RG(3)
+    case 4: LMR_RG(4)
+    default: return nullptr;
+  }
+#undef LMR_RG
+}
+
+}  // namespace
+
+int batch_tile_rows() { return kTY; }
+int batch_block_threads() { return kNT; }
+
+const void* batch_kernel(lmr_dtype t, int box_radius, int gauss_radius) {
+  return t == LMR_BF16 ? kernel_for<uint16_t>(box_radius, gauss_radius)
+                       : kernel_for<float>(box_radius, gauss_radius);
+}
+
+hipError_t launch_batch_attempt(const void* kernel, int grid, const BatchPair* pairs,
+                                int npairs, int n_vox_items, int n_tiles, BatchCtl* ctl,
+                                const DecideParams& dp, unsigned long long timeout,
+                                hipStream_t s) {
+  void* args[] = {&pairs, &npairs, &n_vox_items, &n_tiles, &ctl,
+                  const_cast<DecideParams*>(&dp), &timeout};
+  return hipLaunchKernel(kernel, dim3(grid), dim3(kNT), args, 0, s);
+}
+
+}  // namespace lmr

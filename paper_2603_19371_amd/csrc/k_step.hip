@@ -6,7 +6,9 @@
 //             Mw = M o (Id + u~)  (the candidate's warped image, fused here)
 //   k_decide  FP64 loss reduction, damping rule and rejection test
 //             (Sec. 2.2, eq. lambda-update / eq. delta-loss; Sec. 3.4, eq. rejection)
+#include "decide.h"
 #include "lmr_internal.h"
+#include "update.h"
 
 #include <math.h>
 
@@ -50,57 +52,23 @@ __global__ void __launch_bounds__(kBX* kBY)
              const float* __restrict__ G, float* U0, float* U1,
              const float* u_in, float* u_out, float r_arg, float lam_arg,
              float eps, int compositive, float* __restrict__ Mw) {
-  const float* uin;
-  float* uo;
-  float r, lam;
+  UpdateArgs a;
   if (st) {
     if (st->stalled) return;
-    const int cur = st->cur;
-    uin = cur ? U1 : U0;
-    uo = cur ? U0 : U1;
-    r = static_cast<float>(st->r);
-    lam = static_cast<float>(st->lambda);
+    a = update_args_from_state(st, U0, U1, G, Mw, eps, compositive);
   } else {
-    uin = u_in;
-    uo = u_out;
-    r = r_arg;
-    lam = lam_arg;
+    a.uin = u_in;
+    a.uo = u_out;
+    a.G = G;
+    a.Mw = Mw;
+    a.r = r_arg;
+    a.lam = lam_arg;
+    a.eps = eps;
+    a.compositive = compositive;
   }
   int x, y, z, i;
   if (!voxel(g, x, y, z, i)) return;
-  const int N = static_cast<int>(g.N);
-  const float g0 = G[i], g1 = G[N + i], g2 = G[2 * N + i];
-  const float s = -r / (g0 * g0 + g1 * g1 + g2 * g2 + lam);
-  const float e0 = eps * (s * g0), e1 = eps * (s * g1), e2 = eps * (s * g2);
-  float b0, b1, b2;
-  if (compositive) {
-    const BCell c = make_bcell(g, x, y, z, e0, e1, e2);
-    float v[8];
-    bcorners<float>(make_rbuf_n(uin, N), g, c, v);
-    b0 = binterp(c, v, nullptr);
-    bcorners<float>(make_rbuf_n(uin + N, N), g, c, v);
-    b1 = binterp(c, v, nullptr);
-    bcorners<float>(make_rbuf_n(uin + 2 * N, N), g, c, v);
-    b2 = binterp(c, v, nullptr);
-  } else {
-    b0 = uin[i];
-    b1 = uin[N + i];
-    b2 = uin[2 * N + i];
-  }
-  const float n0 = e0 + b0, n1 = e1 + b1, n2 = e2 + b2;
-  uo[i] = n0;
-  uo[N + i] = n1;
-  uo[2 * N + i] = n2;
-  if (M) {
-    const BCell c = make_bcell(g, x, y, z, n0, n1, n2);
-    float v[8];
-    bcorners<T>(make_rbuf_n(M, N), g, c, v);
-    Mw[i] = binterp(c, v, nullptr);
-  }
-}
-
-__device__ __forceinline__ double clampd(double v, double lo, double hi) {
-  return v < lo ? lo : (v > hi ? hi : v);
+  update_voxel(M, g, a, x, y, z);
 }
 
 constexpr int kDecideThreads = 256;
@@ -109,69 +77,7 @@ __global__ void __launch_bounds__(kDecideThreads)
     k_decide(DevState* st, const double* __restrict__ partials, int nparts,
              long long N, DecideParams dp, int mode, int force, double lambda0,
              double* probe) {
-  if (mode == 0 && st->stalled) {
-    if (threadIdx.x == 0) {
-      st->accepted = 0;
-    }
-    return;
-  }
-  __shared__ double sh[kDecideThreads];
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nparts; k += kDecideThreads) s += partials[k];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = kDecideThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  const double L = -sh[0] / static_cast<double>(N);
-  if (mode == 2) {
-    *probe = L;
-    return;
-  }
-  if (mode == 1) {
-    st->lambda = lambda0;
-    st->loss = L;
-    st->loss_prev = L;
-    st->cand_loss = L;
-    st->r = 1.0 + L;
-    st->n_hist = 1;
-    st->retries = 0;
-    st->accepted = 1;
-    st->stalled = 0;
-    st->cur = 0;
-    st->attempts = 0;
-    return;
-  }
-  st->cand_loss = L;
-  st->attempts += 1;
-  int acc;
-  if (force >= 0) {
-    acc = force ? 1 : 0;
-  } else if (!isfinite(L)) {
-    acc = 0;
-  } else if (dp.tau < 0.0) {
-    acc = 1;
-  } else {
-    double ref = st->n_hist >= 2 ? fabs(st->loss - st->loss_prev) : 0.0;
-    acc = !((L - st->loss) > dp.tau * ref);
-  }
-  if (acc) {
-    double f = (L > st->loss) ? dp.lambda_inc : dp.lambda_dec;
-    st->lambda = clampd(f * st->lambda, dp.lambda_min, dp.lambda_max);
-    st->loss_prev = st->loss;
-    st->loss = L;
-    st->r = 1.0 + L;
-    st->n_hist += 1;
-    st->retries = 0;
-    st->cur = 1 - st->cur;
-  } else {
-    st->lambda = clampd(dp.lambda_inc * st->lambda, dp.lambda_min, dp.lambda_max);
-    st->retries += 1;
-    if (st->retries >= dp.max_retries && st->lambda >= dp.lambda_max) st->stalled = 1;
-  }
-  st->accepted = acc;
+  decide_block<kDecideThreads>(st, partials, nparts, N, dp, mode, force, lambda0, probe);
 }
 
 __global__ void k_copy_cur(const DevState* __restrict__ st, const float* U0,
@@ -188,8 +94,20 @@ __global__ void k_fill(float* __restrict__ dst, long long n, float v) {
     dst[i] = v;
 }
 
+__global__ void k_set_state(DevState* st, DevState v) {
+  v.cur = st->cur;
+  *st = v;
+}
+
 dim3 vox_grid(const Geom& g) {
   return dim3((g.nx + kBX - 1) / kBX, (g.ny + kBY - 1) / kBY, g.nz);
+}
+
+unsigned flat_grid(long long n) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  return static_cast<unsigned>(blocks);
 }
 
 }  // namespace
@@ -211,15 +129,16 @@ hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
                          float* U0, float* U1, const float* u_in, float* u_out,
                          double r, double lambda, float* Mw, hipStream_t s) {
   dim3 blk(kBX, kBY);
-  float rf = static_cast<float>(r), lf = static_cast<float>(lambda);
+  const float rf = static_cast<float>(r), lf = static_cast<float>(lambda);
+  const float eps = static_cast<float>(p.step_eps);
   if (t == LMR_BF16)
     hipLaunchKernelGGL(k_update<uint16_t>, vox_grid(g), blk, 0, s,
-                       static_cast<const uint16_t*>(M), g, st, G, U0, U1, u_in,
-                       u_out, rf, lf, (float)p.step_eps, p.compositive, Mw);
+                       static_cast<const uint16_t*>(M), g, st, G, U0, U1, u_in, u_out,
+                       rf, lf, eps, p.compositive, Mw);
   else
     hipLaunchKernelGGL(k_update<float>, vox_grid(g), blk, 0, s,
-                       static_cast<const float*>(M), g, st, G, U0, U1, u_in, u_out,
-                       rf, lf, (float)p.step_eps, p.compositive, Mw);
+                       static_cast<const float*>(M), g, st, G, U0, U1, u_in, u_out, rf,
+                       lf, eps, p.compositive, Mw);
   return hipGetLastError();
 }
 
@@ -233,19 +152,10 @@ hipError_t launch_decide(DevState* st, const double* partials, int nparts,
 
 hipError_t launch_copy_cur(const DevState* st, const float* U0, const float* U1,
                            float* dst, long long n, hipStream_t s) {
-  long long blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_copy_cur, dim3((unsigned)blocks), dim3(256), 0, s, st, U0,
-                     U1, dst, n);
+  hipLaunchKernelGGL(k_copy_cur, dim3(flat_grid(n)), dim3(256), 0, s, st, U0, U1, dst,
+                     n);
   return hipGetLastError();
 }
-
-namespace {
-__global__ void k_set_state(DevState* st, DevState v) {
-  v.cur = st->cur;
-  *st = v;
-}
-}  // namespace
 
 hipError_t launch_set_state(DevState* st, const DevState& v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_state, dim3(1), dim3(1), 0, s, st, v);
@@ -253,10 +163,7 @@ hipError_t launch_set_state(DevState* st, const DevState& v, hipStream_t s) {
 }
 
 hipError_t launch_fill(float* dst, long long n, float v, hipStream_t s) {
-  long long blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, dst, n, v);
+  hipLaunchKernelGGL(k_fill, dim3(flat_grid(n)), dim3(256), 0, s, dst, n, v);
   return hipGetLastError();
 }
 

@@ -1,0 +1,49 @@
+// Internal structures of the batched persistent form (k_batch.hip, api_batch.cpp).
+#pragma once
+
+#include "lmr_internal.h"
+#include "stencil.h"
+
+namespace lmr {
+
+// One pair of a batch as the persistent kernel sees it (device memory).
+struct BatchPair {
+  Geom g;
+  const void* F;
+  const void* M;
+  float* U0;
+  float* U1;
+  float* G;
+  float* graw;
+  float* maps;
+  float* Mw;
+  double* partials;  // one slot per stencil tile of this pair
+  DevState* st;
+  Tiling t;          // stencil tiling of this pair
+  int vox0;          // first update work item of this pair
+  int tile0;         // first stencil work item of this pair
+  float eps;
+  int compositive;
+  double inv_n, cc_eps;
+  float gw[16];      // Gaussian taps, 2R+1 <= 9 used
+};
+
+// Grid-barrier state and the timeout flag of the persistent kernel.
+struct BatchCtl {
+  unsigned count;
+  unsigned gen;
+  int error;
+  int pad_;
+};
+
+int batch_tile_rows();
+int batch_block_threads();
+// The persistent kernel for (image type, box radius 1..4, Gaussian radius
+// 0..4), or null when that combination is not instantiated.
+const void* batch_kernel(lmr_dtype t, int box_radius, int gauss_radius);
+hipError_t launch_batch_attempt(const void* kernel, int grid, const BatchPair* pairs,
+                                int npairs, int n_vox_items, int n_tiles, BatchCtl* ctl,
+                                const DecideParams& dp, unsigned long long timeout,
+                                hipStream_t s);
+
+}  // namespace lmr

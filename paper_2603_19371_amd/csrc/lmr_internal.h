@@ -111,22 +111,26 @@ __device__ __forceinline__ void corners(const T* __restrict__ V, const Geom& g,
 
 // Interpolated value from the corners; grad (may be null) receives the
 // derivative of the interpolant on the cell.
+// Each weighted pair a*x + b*y is one product and one fused multiply-add.
+__device__ __forceinline__ float lerp2(float a, float x, float b, float y) {
+  return fmaf(b, y, a * x);
+}
 __device__ __forceinline__ float interp(const Cell& c, const float v[8], float* grad) {
   const float gx0 = 1.0f - c.fx, gy0 = 1.0f - c.fy, gz0 = 1.0f - c.fz;
-  const float c00 = gx0 * v[0] + c.fx * v[1];
-  const float c01 = gx0 * v[2] + c.fx * v[3];
-  const float c10 = gx0 * v[4] + c.fx * v[5];
-  const float c11 = gx0 * v[6] + c.fx * v[7];
-  const float c0 = gy0 * c00 + c.fy * c01;
-  const float c1 = gy0 * c10 + c.fy * c11;
+  const float c00 = lerp2(gx0, v[0], c.fx, v[1]);
+  const float c01 = lerp2(gx0, v[2], c.fx, v[3]);
+  const float c10 = lerp2(gx0, v[4], c.fx, v[5]);
+  const float c11 = lerp2(gx0, v[6], c.fx, v[7]);
+  const float c0 = lerp2(gy0, c00, c.fy, c01);
+  const float c1 = lerp2(gy0, c10, c.fy, c11);
   if (grad) {
     const float d00 = v[1] - v[0], d01 = v[3] - v[2];
     const float d10 = v[5] - v[4], d11 = v[7] - v[6];
-    grad[0] = gz0 * (gy0 * d00 + c.fy * d01) + c.fz * (gy0 * d10 + c.fy * d11);
-    grad[1] = gz0 * (c01 - c00) + c.fz * (c11 - c10);
+    grad[0] = lerp2(gz0, lerp2(gy0, d00, c.fy, d01), c.fz, lerp2(gy0, d10, c.fy, d11));
+    grad[1] = lerp2(gz0, c01 - c00, c.fz, c11 - c10);
     grad[2] = c1 - c0;
   }
-  return gz0 * c0 + c.fz * c1;
+  return lerp2(gz0, c0, c.fz, c1);
 }
 
 // Trilinear sample of V at (x+dx, y+dy, z+dz) with zero padding.
@@ -181,12 +185,15 @@ __device__ __forceinline__ void bst(const RBuf& b, unsigned i, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), b.r, i * 4u, 0, 0);
 }
 
-// The trilinear cell addressed through buffers: the eight corner offsets are
-// formed in 32-bit arithmetic and every corner is loaded unconditionally; a
-// corner outside the volume along any axis is then replaced by 0.
+// The trilinear cell addressed through buffers.  Each corner coordinate is
+// clamped into the volume, so all eight loads are in range and issued
+// unconditionally; a corner that lies outside the volume along any axis is
+// then replaced by 0.  (Offsets are never formed by wrap-around: adjacent
+// loads may be fused into one wider access, which the hardware range-checks
+// as a whole.)
 struct BCell {
   float fx, fy, fz;
-  unsigned base;           // linear index of the lower corner (wraps if outside)
+  unsigned o[8];           // corner (i, j, k) at o[4k + 2j + i]
   unsigned char m;         // bit 4k+2j+i: corner (i, j, k) inside the volume
 };
 
@@ -197,10 +204,22 @@ __device__ __forceinline__ BCell make_bcell(const Geom& g, int x, int y, int z, 
   cell(x, dx, x0, c.fx);
   cell(y, dy, y0, c.fy);
   cell(z, dz, z0, c.fz);
-  const unsigned ux = (unsigned)x0, uy = (unsigned)y0, uz = (unsigned)z0;
-  const bool x0i = ux < (unsigned)g.nx, x1i = ux + 1u < (unsigned)g.nx;
-  const bool y0i = uy < (unsigned)g.ny, y1i = uy + 1u < (unsigned)g.ny;
-  const bool z0i = uz < (unsigned)g.nz, z1i = uz + 1u < (unsigned)g.nz;
+  const bool x0i = (unsigned)x0 < (unsigned)g.nx, x1i = (unsigned)(x0 + 1) < (unsigned)g.nx;
+  const bool y0i = (unsigned)y0 < (unsigned)g.ny, y1i = (unsigned)(y0 + 1) < (unsigned)g.ny;
+  const bool z0i = (unsigned)z0 < (unsigned)g.nz, z1i = (unsigned)(z0 + 1) < (unsigned)g.nz;
+  const int xa = min(max(x0, 0), g.nx - 1), xb = min(max(x0 + 1, 0), g.nx - 1);
+  const int ya = min(max(y0, 0), g.ny - 1), yb = min(max(y0 + 1, 0), g.ny - 1);
+  const int za = min(max(z0, 0), g.nz - 1), zb = min(max(z0 + 1, 0), g.nz - 1);
+  const int r00 = (za * g.ny + ya) * g.nx, r01 = (za * g.ny + yb) * g.nx;
+  const int r10 = (zb * g.ny + ya) * g.nx, r11 = (zb * g.ny + yb) * g.nx;
+  c.o[0] = r00 + xa;
+  c.o[1] = r00 + xb;
+  c.o[2] = r01 + xa;
+  c.o[3] = r01 + xb;
+  c.o[4] = r10 + xa;
+  c.o[5] = r10 + xb;
+  c.o[6] = r11 + xa;
+  c.o[7] = r11 + xb;
   c.m = 0;
 #pragma unroll
   for (int k = 0; k < 2; ++k)
@@ -209,19 +228,15 @@ __device__ __forceinline__ BCell make_bcell(const Geom& g, int x, int y, int z, 
 #pragma unroll
       for (int i = 0; i < 2; ++i)
         if ((i ? x1i : x0i) && (j ? y1i : y0i) && (k ? z1i : z0i)) c.m |= 1u << (4 * k + 2 * j + i);
-  c.base = (uz * (unsigned)g.ny + uy) * (unsigned)g.nx + ux;
   return c;
 }
 
 template <typename T>
-__device__ __forceinline__ void bcorners(const RBuf& b, const Geom& g, const BCell& c,
+__device__ __forceinline__ void bcorners(const RBuf& b, const Geom&, const BCell& c,
                                          float v[8]) {
-  const unsigned sy = (unsigned)g.nx, sz = (unsigned)g.nx * (unsigned)g.ny;
-  const unsigned o[8] = {c.base,      c.base + 1,      c.base + sy,      c.base + sy + 1,
-                         c.base + sz, c.base + sz + 1, c.base + sz + sy, c.base + sz + sy + 1};
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const float t = bld<T>(b, o[q]);
+    const float t = bld<T>(b, c.o[q]);
     v[q] = (c.m >> q) & 1u ? t : 0.0f;
   }
 }
@@ -292,6 +307,10 @@ hipError_t launch_avgpool(const void* in, lmr_dtype t, int nz, int ny, int nx, i
                           float* out, hipStream_t s);
 hipError_t launch_upsample_field(const float* uc, int nzc, int nyc, int nxc, float* uf,
                                  hipStream_t s);
+// *count = number of voxels with det(I + grad u) <= 0; det (may be null)
+// receives the determinant map.
+hipError_t launch_folds(const float* u, const Geom& g, unsigned long long* count,
+                        float* det, hipStream_t s);
 // Overwrite every field of *st except `cur` with the fields of v.
 hipError_t launch_set_state(DevState* st, const DevState& v, hipStream_t s);
 // dst[0..n) = v (a kernel, so that graph captures hold no memset node).

@@ -1,0 +1,369 @@
+// Separable 3D stencils of one LM attempt on a shared 2.5D framework, as
+// device functions used by the per-pair kernels (k_stencil.hip) and by the
+// batched persistent kernel (k_batch.hip).
+//
+//   FwdPol    LNCC forward: box sums of F, Mw, F^2, Mw^2, F Mw over the w^3
+//             window (zero padding, divisor w^3), cc = s_FM^2/(s_FF s_MM + eps),
+//             adjoint maps alpha = 2 s_FM/D, alpha mu_F, beta = -s_FM^2 s_FF/D^2,
+//             beta mu_M, and one FP64 partial sum of cc per tile.
+//   BwdPol    LNCC backward: box sums of the four maps give
+//             d(sum cc)/dMw_j = (F_j B(alpha) - B(alpha mu_F) + 2 Mw_j B(beta)
+//                                - 2 B(beta mu_M)) / w^3,
+//             times the trilinear derivative of M at x + u(x) (warp backward);
+//             the result is g = N dL/du with L = -mean cc.
+//   SmoothPol Gaussian of the raw gradient (Eulerian descent, Sec. 2.1).
+//
+// A tile is a 32 x TY column of outputs over a chunk of z planes.  For each
+// input plane the block stages a (TY+2R) x (32+2R) halo tile of the raw FP32
+// inputs in LDS (the next plane is already in flight in registers while the
+// current one is reduced), reduces along y (expanding the raw inputs into the
+// accumulated channels: for the forward pass the exact products F^2, Mw^2,
+// F Mw in FP64) and then along x, and keeps the last 2R+1 plane sums in a
+// register ring.  Box sums run a running sum through the ring; the Gaussian
+// sums it with its taps.
+#pragma once
+
+#include "lmr_internal.h"
+
+namespace lmr {
+
+constexpr int kTX = 32;
+// element index whose byte offset lies beyond any channel (< 2^30 voxels)
+constexpr unsigned kFarIndex = 0x3FFFFFFFu;
+
+struct Tiling {
+  int ty, tiles_x, tiles_y, nchunks, cz;
+  __host__ __device__ int tiles() const { return tiles_x * tiles_y * nchunks; }
+};
+
+// z-chunk: long enough that the 2R halo planes of a chunk stay a small
+// fraction when the volume is large, short enough that small volumes still
+// give a few hundred tiles.  target_tiles and min_cz are tuning knobs.
+__host__ __device__ inline Tiling make_tiling(int nz, int ny, int nx, int ty,
+                                              int target_tiles = 2048, int min_cz = 16) {
+  Tiling t;
+  t.ty = ty;
+  t.tiles_x = (nx + kTX - 1) / kTX;
+  t.tiles_y = (ny + ty - 1) / ty;
+  const int cols = t.tiles_x * t.tiles_y;
+  const int want = (target_tiles + cols - 1) / cols;
+  int cz = (nz + want - 1) / want;
+  if (cols * ((nz + min_cz - 1) / min_cz) >= target_tiles / 2 && cz < min_cz) cz = min_cz;
+  if (cz < 4) cz = 4;
+  if (cz > nz) cz = nz;
+  t.cz = cz;
+  t.nchunks = (nz + cz - 1) / cz;
+  return t;
+}
+
+// Runs the stencil over tile (x0, y0, z0..z1) with the whole block.
+template <int R, int TY, class P>
+__device__ __forceinline__ void stencil_tile(const P& pol, const Geom& g, int x0, int y0,
+                                             int z0, int z1, typename P::Local& loc) {
+  using A = typename P::Acc;
+  constexpr int NR = P::NRAW, NC = P::NCH;
+  constexpr int W = 2 * R + 1, LX = kTX + 2 * R, LY = TY + 2 * R, NT = kTX * TY;
+  constexpr int NPOS = LX * LY, PER = (NPOS + NT - 1) / NT;
+  __shared__ float s_in[NR][LY][LX];
+  __shared__ A s_y[NC][TY][LX];
+
+  const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
+  const int gx = x0 + lx, gy = y0 + ly;
+  const bool own = gx < g.nx && gy < g.ny;
+  const int plane = g.ny * g.nx;
+
+  // positions of the halo tile this thread stages
+  int pidx[PER];
+  bool pin[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int i = threadIdx.x + p * NT;
+    const int yy = i / LX, xx = i - yy * LX;
+    const int gyy = y0 - R + yy, gxx = x0 - R + xx;
+    pin[p] = i < NPOS && (unsigned)gyy < (unsigned)g.ny && (unsigned)gxx < (unsigned)g.nx;
+    pidx[p] = pin[p] ? gyy * g.nx + gxx : 0;
+  }
+  // Branch-free staging: a padding position (outside the volume in x, y or z)
+  // reads kFarIndex, whose offset lies beyond the buffer and reads 0.
+  float pre[PER][NR];
+  auto fetch = [&](int zi) {
+    const bool zin = (unsigned)zi < (unsigned)g.nz;
+    const unsigned zoff = zin ? static_cast<unsigned>(zi * plane) : 0u;
+#pragma unroll
+    for (int p = 0; p < PER; ++p)
+      pol.load(loc, (zin && pin[p]) ? zoff + static_cast<unsigned>(pidx[p]) : kFarIndex,
+               pre[p]);
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int i = threadIdx.x + p * NT;
+      if (i < NPOS) {
+        const int yy = i / LX, xx = i - yy * LX;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) s_in[c][yy][xx] = pre[p][c];
+      }
+    }
+  };
+
+  A ring[W][NC], run[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    run[c] = A(0);
+#pragma unroll
+    for (int k = 0; k < W; ++k) ring[k][c] = A(0);
+  }
+
+  const int zend = z1 + R;
+  int zi = z0 - R;
+  fetch(zi);
+  while (zi < zend) {
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+      if (zi < zend) {
+        commit();
+        if (zi + 1 < zend) fetch(zi + 1);
+        __syncthreads();
+        for (int i = threadIdx.x; i < TY * LX; i += NT) {
+          const int yy = i / LX, xx = i - yy * LX;
+          A a[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) a[c] = A(0);
+#pragma unroll
+          for (int k = 0; k < W; ++k) {
+            float r[NR];
+#pragma unroll
+            for (int c = 0; c < NR; ++c) r[c] = s_in[c][yy + k][xx];
+            pol.accum(a, r, k);
+          }
+#pragma unroll
+          for (int c = 0; c < NC; ++c) s_y[c][yy][xx] = a[c];
+        }
+        __syncthreads();
+        A pl[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pl[c] = A(0);
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) pl[c] = fma(A(pol.wt(k)), s_y[c][ly][lx + k], pl[c]);
+        A sm[NC];
+        if (P::kBox) {
+          // ring[s] holds the plane that entered W steps ago
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            run[c] += pl[c] - ring[s][c];
+            ring[s][c] = pl[c];
+            sm[c] = run[c];
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            ring[s][c] = pl[c];
+            sm[c] = A(0);
+          }
+          // planes zi-2R .. zi sit in slots s+1 .. s+W (mod W)
+#pragma unroll
+          for (int k = 0; k < W; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+              sm[c] = fma(A(pol.wt(k)), ring[(s + 1 + k) % W][c], sm[c]);
+        }
+        const int zo = zi - R;
+        if (zo >= z0 && own) pol.emit(loc, zo * plane + gy * g.nx + gx, gx, gy, zo, sm);
+      }
+      ++zi;
+    }
+  }
+}
+
+// Block sum of one double per thread; thread 0 writes it to *out.
+template <int NT>
+__device__ __forceinline__ void block_sum_to(double v, double* out) {
+  __shared__ double red[NT / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) s += red[k];
+    *out = s;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------- forward (P2)
+template <typename T, int NT>
+struct FwdPol {
+  using Acc = double;
+  static constexpr int NRAW = 2, NCH = 5;
+  static constexpr bool kBox = true;
+  const T* __restrict__ F;
+  const float* __restrict__ Mw;
+  float* __restrict__ maps;
+  float* __restrict__ cc;
+  double* __restrict__ partials;
+  int N;
+  double inv_n, eps;
+  struct Local {
+    double sum;
+    RBuf bF, bM;
+  };
+
+  __device__ static constexpr double wt(int) { return 1.0; }
+  __device__ Local begin_block(const DevState*) const {
+    return Local{0.0, make_rbuf_n(F, N), make_rbuf_n(Mw, N)};
+  }
+  __device__ void load(const Local& l, unsigned i, float v[2]) const {
+    v[0] = bld<T>(l.bF, i);
+    v[1] = bld<float>(l.bM, i);
+  }
+  __device__ void accum(double a[5], const float r[2], int) const {
+    const double f = r[0], m = r[1];
+    a[0] += f;
+    a[1] += m;
+    a[2] = fma(f, f, a[2]);
+    a[3] = fma(m, m, a[3]);
+    a[4] = fma(f, m, a[4]);
+  }
+  __device__ void emit(Local& loc, int i, int, int, int, const double S[5]) const {
+    const double muF = S[0] * inv_n, muM = S[1] * inv_n;
+    const double sfm = S[4] * inv_n - muF * muM;
+    const double sff = S[2] * inv_n - muF * muF;
+    const double smm = S[3] * inv_n - muM * muM;
+    const double iD = 1.0 / (sff * smm + eps);
+    const double c = sfm * sfm * iD;
+    const double alpha = 2.0 * sfm * iD;
+    const double beta = -c * sff * iD;
+    maps[i] = static_cast<float>(alpha);
+    maps[N + i] = static_cast<float>(alpha * muF);
+    maps[2 * N + i] = static_cast<float>(beta);
+    maps[3 * N + i] = static_cast<float>(beta * muM);
+    if (cc) cc[i] = static_cast<float>(c);
+    loc.sum += c;
+  }
+  // partial sum of cc of the tile just processed, to partials[slot]
+  __device__ void end_tile(Local& loc, int slot) const {
+    block_sum_to<NT>(loc.sum, partials + slot);
+    loc.sum = 0.0;
+  }
+};
+
+// ------------------------------------------------------------ backward (P4)
+template <typename T>
+struct BwdPol {
+  using Acc = double;
+  static constexpr int NRAW = 4, NCH = 4;
+  static constexpr bool kBox = true;
+  const T* __restrict__ F;
+  const T* __restrict__ M;
+  const float* __restrict__ Mw;
+  const float* __restrict__ maps;
+  const float* U0;  // field ping-pong (state mode: the field is U[cur])
+  const float* U1;
+  const float* u_explicit;  // the field when no state is given
+  float* __restrict__ graw;
+  Geom g;
+  double inv_n;
+  struct Local {
+    RBuf bmap[4];
+    RBuf bM;
+    const float* u;
+  };
+
+  __device__ static constexpr double wt(int) { return 1.0; }
+  __device__ Local begin_block(const DevState* st) const {
+    const int N = static_cast<int>(g.N);
+    Local l;
+    l.u = st ? (st->cur ? U1 : U0) : u_explicit;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) l.bmap[c] = make_rbuf_n(maps + c * N, N);
+    l.bM = make_rbuf_n(M, N);
+    return l;
+  }
+  __device__ void load(const Local& l, unsigned i, float v[4]) const {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = bld<float>(l.bmap[c], i);
+  }
+  __device__ void accum(double a[4], const float r[4], int) const {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] += static_cast<double>(r[c]);
+  }
+  __device__ void emit(const Local& loc, int i, int x, int y, int z,
+                       const double B[4]) const {
+    const int N = static_cast<int>(g.N);
+    const float* u = loc.u;
+    const double fj = ldf(F, i), mj = Mw[i];
+    const double dS = (fj * B[0] - B[1] + 2.0 * mj * B[2] - 2.0 * B[3]) * inv_n;
+    const float d = static_cast<float>(dS);
+    float gm[3], v[8];
+    const BCell c = make_bcell(g, x, y, z, u[i], u[N + i], u[2 * N + i]);
+    bcorners<T>(loc.bM, g, c, v);
+    binterp(c, v, gm);
+    graw[i] = -d * gm[0];
+    graw[N + i] = -d * gm[1];
+    graw[2 * N + i] = -d * gm[2];
+  }
+  __device__ void end_tile(Local&, int) const {}
+};
+
+// ----------------------------------------------------------- smoothing (P5)
+template <int R>
+struct SmoothPol {
+  using Acc = float;
+  static constexpr int NRAW = 3, NCH = 3;
+  static constexpr bool kBox = false;
+  const float* __restrict__ in;
+  float* __restrict__ out;
+  int N;
+  float w[2 * R + 1];
+  struct Local {
+    RBuf b[3];
+  };
+
+  __device__ float wt(int k) const { return w[k]; }
+  __device__ Local begin_block(const DevState*) const {
+    return Local{{make_rbuf_n(in, N), make_rbuf_n(in + N, N), make_rbuf_n(in + 2 * N, N)}};
+  }
+  __device__ void load(const Local& l, unsigned i, float v[3]) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = bld<float>(l.b[c], i);
+  }
+  __device__ void accum(float a[3], const float r[3], int k) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a[c] = fmaf(w[k], r[c], a[c]);
+  }
+  __device__ void emit(Local&, int i, int, int, int, const float S[3]) const {
+    out[i] = S[0];
+    out[N + i] = S[1];
+    out[2 * N + i] = S[2];
+  }
+  __device__ void end_tile(Local&, int) const {}
+};
+
+// Normalised Gaussian taps k in [-R, R] (host side).
+template <int R>
+inline void gauss_taps(double sigma, float* w) {
+  double t[2 * R + 1], tot = 0.0;
+  for (int k = -R; k <= R; ++k) {
+    t[k + R] = R == 0 ? 1.0 : exp(-(double)k * k / (2.0 * sigma * sigma));
+    tot += t[k + R];
+  }
+  for (int k = 0; k <= 2 * R; ++k) w[k] = static_cast<float>(t[k] / tot);
+}
+
+// Decode a tile index (x fastest, then y, then z chunk).
+__device__ __forceinline__ void tile_origin(const Tiling& t, int b, int ty, int& x0,
+                                            int& y0, int& z0) {
+  const int tx_i = b % t.tiles_x;
+  const int ty_i = (b / t.tiles_x) % t.tiles_y;
+  const int ch = b / (t.tiles_x * t.tiles_y);
+  x0 = tx_i * kTX;
+  y0 = ty_i * ty;
+  z0 = ch * t.cz;
+}
+
+}  // namespace lmr

@@ -1,0 +1,76 @@
+// Per-voxel step of one LM attempt, shared by the per-pair update kernel and
+// the batched persistent kernel:
+//   du = -r g / (|g|^2 + lambda)                 (Sec. 2.2, eq. tile1)
+//   u~ = eps du + u o (Id + eps du)              (Sec. 2.1, eq. compositive)
+//   Mw = M o (Id + u~)                           (the candidate's warped image)
+#pragma once
+
+#include "lmr_internal.h"
+
+namespace lmr {
+
+struct UpdateArgs {
+  const float* uin;  // accepted field [3][N]
+  float* uo;         // candidate field [3][N]
+  const float* G;    // smoothed gradient of the accepted field [3][N]
+  float* Mw;         // warped moving image at the candidate (null: skip)
+  float r, lam, eps;
+  int compositive;
+};
+
+template <typename T>
+__device__ __forceinline__ void update_voxel(const T* __restrict__ M, const Geom& g,
+                                             const UpdateArgs& a, int x, int y, int z) {
+  const int N = static_cast<int>(g.N);
+  const int i = (z * g.ny + y) * g.nx + x;
+  const float g0 = a.G[i], g1 = a.G[N + i], g2 = a.G[2 * N + i];
+  const float s = -a.r / fmaf(g2, g2, fmaf(g1, g1, fmaf(g0, g0, a.lam)));
+  const float e0 = a.eps * (s * g0), e1 = a.eps * (s * g1), e2 = a.eps * (s * g2);
+  float b0, b1, b2;
+  if (a.compositive) {
+    const BCell c = make_bcell(g, x, y, z, e0, e1, e2);
+    float v[8];
+    bcorners<float>(make_rbuf_n(a.uin, N), g, c, v);
+    b0 = binterp(c, v, nullptr);
+    bcorners<float>(make_rbuf_n(a.uin + N, N), g, c, v);
+    b1 = binterp(c, v, nullptr);
+    bcorners<float>(make_rbuf_n(a.uin + 2 * N, N), g, c, v);
+    b2 = binterp(c, v, nullptr);
+  } else {
+    b0 = a.uin[i];
+    b1 = a.uin[N + i];
+    b2 = a.uin[2 * N + i];
+  }
+  const float n0 = e0 + b0, n1 = e1 + b1, n2 = e2 + b2;
+  a.uo[i] = n0;
+  a.uo[N + i] = n1;
+  a.uo[2 * N + i] = n2;
+  if (M && a.Mw) {
+    const BCell c = make_bcell(g, x, y, z, n0, n1, n2);
+    float v[8];
+    bcorners<T>(make_rbuf_n(M, N), g, c, v);
+    a.Mw[i] = binterp(c, v, nullptr);
+  }
+}
+
+// The update arguments of an attempt in state mode: the accepted field is
+// U[cur], the candidate goes to the other buffer, r and lambda come from the
+// device state.
+__device__ __forceinline__ UpdateArgs update_args_from_state(const DevState* st,
+                                                             float* U0, float* U1,
+                                                             const float* G, float* Mw,
+                                                             float eps, int compositive) {
+  UpdateArgs a;
+  const int cur = st->cur;
+  a.uin = cur ? U1 : U0;
+  a.uo = cur ? U0 : U1;
+  a.G = G;
+  a.Mw = Mw;
+  a.r = static_cast<float>(st->r);
+  a.lam = static_cast<float>(st->lambda);
+  a.eps = eps;
+  a.compositive = compositive;
+  return a;
+}
+
+}  // namespace lmr

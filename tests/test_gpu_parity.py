@@ -154,6 +154,28 @@ def test_update_matches_oracle(L, orc, compositive):
     assert e < 2e-5, e
 
 
+@pytest.mark.parametrize("sign", [-1.0, 1.0])
+def test_gathers_at_volume_corners(L, orc, sign):
+    """Displacements of one sign everywhere put the trilinear cell of the
+    first (sign < 0) or last (sign > 0) voxel half outside the volume along
+    all three axes; warp and update must still read the in-volume corner."""
+    shape = (9, 10, 11)
+    rng = np.random.default_rng(40)
+    M = rng.uniform(0.5, 1.5, shape).astype(np.float32)
+    u = np.full((3,) + shape, 0.3 * sign, np.float32)
+    got = host(L.warp(dev(M), dev(u)))
+    ref = orc.warp(M, u)
+    e = np.abs(got - ref).max()
+    assert e < 1e-6, e
+    uu = rng.uniform(0.5, 1.5, (3,) + shape).astype(np.float32)
+    g = np.full((3,) + shape, -sign, np.float32)      # du has the sign of `sign`
+    ctx = L.Context(shape)
+    out = host(ctx.update(dev(uu), dev(g), 0.4, 0.1))
+    ref = orc.integrate(uu, orc.closed_form(g, 0.4, 0.1), 1.0, 1)
+    e = np.abs(out - ref).max()
+    assert e < 2e-6, e
+
+
 # ------------------------------------------------------------------ decision
 def test_decide_probe_matches_golden_tables(L):
     import json

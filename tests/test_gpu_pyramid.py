@@ -60,3 +60,20 @@ def test_pyramid_run_with_oracle_decisions(L, orc):
     assert err < 1e-4, err
     for l, (_, n) in enumerate(levels):
         assert pyr.level(l).state()["attempts"] == n
+
+
+@pytest.mark.parametrize("shape", [(9, 10, 11), (20, 37, 70), (1, 16, 24)])
+def test_folded_count_is_bit_exact(L, orc, shape):
+    """The count is an integer decided in FP64 with the oracle's operation
+    order: it must equal the oracle's count exactly."""
+    from scipy import ndimage as ndi
+    rng = np.random.default_rng(sum(shape))
+    u = ndi.gaussian_filter(rng.standard_normal((3,) + shape), (0, 1, 1, 1)) * 5
+    u = u.astype(np.float32)
+    ctx = L.Context(shape)
+    n, det = ctx.folded_count(dev(u), with_det=True)
+    rn, rdet = orc.folded_count(u.astype(np.float64), with_det=True)
+    assert n == rn
+    assert 0 < n < int(np.prod(shape)) or shape[0] == 1
+    np.testing.assert_allclose(host(det), rdet, rtol=1e-6, atol=1e-6)
+    assert ctx.folded_count(dev(np.zeros((3,) + shape, np.float32))) == 0
