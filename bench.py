@@ -18,6 +18,16 @@ Printed on one JSON line, with
                 same workload (attempts at the full-resolution level).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--workload brain|lung|batch]
+
+The default workload is the brain registration above.  Two more workloads
+print a line of the same form:
+  lung   384^3 lung-CT-like pair with BF16 images (FP32 field, FP64 loss),
+         pyramid 2x/1x with 100/50 attempts;
+  batch  16 brain-like pairs of uneven shapes (4 x 96^3, 4 x 128x160x128,
+         4 x 160x192x224, 4 x 192x160x256) advanced together, one persistent
+         launch per attempt replayed from a HIP graph, tiling autotuned,
+         150 attempts at full resolution.
 """
 from __future__ import annotations
 
@@ -78,7 +88,7 @@ def traffic_for(kernel: str, workload: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(ph, attempts=2):
+def cpu_baseline(F, M, attempts=2, what="the full-resolution level"):
     import numpy as np
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
@@ -86,17 +96,177 @@ def cpu_baseline(ph, attempts=2):
     used = oracle.get_threads()
     p = oracle.Params(window=WINDOW, grad_sigma=SIGMA)
     t0 = time.perf_counter()
-    pr = oracle.Pair(ph.F, ph.M, p).begin(lambda0=1.0)
+    pr = oracle.Pair(F, M, p).begin(lambda0=1.0)
     t1 = time.perf_counter()
     for _ in range(attempts):
         pr.attempt()
     t2 = time.perf_counter()
-    n = int(np.prod(SHAPE))
+    n = int(np.prod(F.shape))
+    sh = "x".join(str(d) for d in F.shape)
     return {"value": n * attempts / (t2 - t1), "unit": "voxel-attempts/s",
             "cores": used, "kind": "oracle",
-            "sample": f"{attempts} LM attempts of the full-resolution level "
-                      f"({SHAPE[0]}x{SHAPE[1]}x{SHAPE[2]}) after begin "
+            "sample": f"{attempts} LM attempts of {what} ({sh}) after begin "
                       f"({t1 - t0:.1f} s), FP64 oracle, {used} threads"}
+
+
+def _pyramid_line(a, F, M, img_dtype, factors, iters, workload, s):
+    """Times `steps` full coarse-to-fine registrations; roofline from the
+    fine level's kernel events."""
+    import numpy as np
+    import torch
+    from paper_2603_19371_amd import _lib
+
+    shape = tuple(F.shape)
+    pyr = _lib.Pyramid(shape, factors, img_dtype=img_dtype, window=WINDOW, grad_sigma=SIGMA)
+    out = torch.empty((3,) + shape, device="cuda")
+    for _ in range(a.warmup):
+        pyr.run(F, M, iters, lambda0=1.0, out=out)
+    torch.cuda.synchronize()
+    fine = pyr.level(len(factors) - 1)
+    fine.profile_start(max_attempts=iters[-1] * a.steps, stride=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        pyr.run(F, M, iters, lambda0=1.0, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = fine.profile_stop()
+
+    per_level = []
+    vox_att = 0
+    for l, f in enumerate(factors):
+        st = pyr.level(l).state()
+        n = int(np.prod([d // f for d in shape]))
+        per_level.append({"factor": f, "voxels": n, "attempts": int(st["attempts"]),
+                          "accepted_loss": st["loss"], "lambda": st["lambda_"]})
+        vox_att += n * int(st["attempts"])
+    elapsed = t1 - t0
+    nfine = int(np.prod(shape))
+    kb = kernel_bytes(s)
+    dom = max((k for k in prof if prof[k]["count"]), key=lambda k: prof[k]["total_ms"])
+    achieved = kb[dom] * nfine / (prof[dom]["avg_ms"] * 1e-3) / 1e9
+    attempt_ms = sum(v["avg_ms"] for v in prof.values() if v["count"])
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_for(dom, workload), "kernel": dom,
+                "algorithmic_bytes_per_launch": kb[dom] * nfine,
+                "mean_launch_ms": round(prof[dom]["avg_ms"], 5),
+                "launches_timed": prof[dom]["count"]}
+    detail = {
+        "levels": per_level,
+        "fine_level_kernel_ms": {k: round(v["avg_ms"], 5) for k, v in prof.items()
+                                 if v["count"]},
+        "fine_level_attempt_ms": round(attempt_ms, 5),
+        "fine_level_voxel_attempts_per_s": round(nfine / (attempt_ms * 1e-3), 1),
+        "fine_level_attempt_algorithmic_frac": round(
+            attempt_bytes(s) * nfine / (attempt_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernel_source_sha": source_sha(),
+    }
+    return vox_att * a.steps / elapsed, elapsed, vox_att, roofline, detail
+
+
+def run_brain(a):
+    import torch
+    from paper_2603_19371_amd import phantoms
+
+    ph = phantoms.brain(SHAPE, seed=0)
+    F = torch.from_numpy(ph.F).cuda()
+    M = torch.from_numpy(ph.M).cuda()
+    workload = "brain160x192x224_f32_w7"
+    value, elapsed, vox_att, roofline, detail = _pyramid_line(
+        a, F, M, torch.float32, FACTORS, ITERS, workload, 4)
+    cpu = None if a.no_cpu_baseline else cpu_baseline(ph.F, ph.M)
+    config = {"workload": "brain-MRI-like phantom 160x192x224, FP32 images and field, "
+                          "LNCC w=7, sigma_g=1, pyramid 4x/2x/1x with 200/100/50 "
+                          "attempts, lambda0=1, x2/x0.5, tau=0",
+              "pairs": 1, "voxel_attempts_per_step": vox_att}
+    return "f32", value, elapsed, config, roofline, cpu, detail
+
+
+def run_lung(a):
+    import numpy as np
+    import torch
+    from paper_2603_19371_amd import phantoms
+
+    shape = (384, 384, 384)
+    ph = phantoms.lung(shape, seed=0)
+    bits = phantoms.to_bf16_rne(ph.F)
+    F = torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16)
+    M = torch.from_numpy(phantoms.to_bf16_rne(ph.M).view(np.int16)).cuda().view(torch.bfloat16)
+    workload = "lung384_bf16_w7"
+    factors, iters = (2, 1), (100, 50)
+    value, elapsed, vox_att, roofline, detail = _pyramid_line(
+        a, F, M, torch.bfloat16, factors, iters, workload, 2)
+    cpu = None
+    if not a.no_cpu_baseline:
+        c = tuple(slice(d // 2 - 64, d // 2 + 64) for d in shape)
+        Fc = phantoms.bf16_to_f32(bits)[c].copy()
+        Mc = phantoms.bf16_to_f32(phantoms.to_bf16_rne(ph.M))[c].copy()
+        cpu = cpu_baseline(Fc, Mc, what="a centred 128^3 crop of the BF16 lung pair")
+    config = {"workload": "lung-CT-like phantom 384^3, BF16 images, FP32 field, FP64 "
+                          "loss reduction, LNCC w=7, sigma_g=1, pyramid 2x/1x with "
+                          "100/50 attempts, lambda0=1, x2/x0.5, tau=0",
+              "pairs": 1, "voxel_attempts_per_step": vox_att}
+    return "bf16", value, elapsed, config, roofline, cpu, detail
+
+
+BATCH_SHAPES = [(96, 96, 96)] * 4 + [(128, 160, 128)] * 4 + [(160, 192, 224)] * 4 + \
+    [(192, 160, 256)] * 4
+BATCH_ITERS = 150
+
+
+def run_batch(a):
+    import numpy as np
+    import torch
+    from paper_2603_19371_amd import _lib, phantoms_torch
+
+    pairs = [phantoms_torch.brain(sh, seed=100 + i) for i, sh in enumerate(BATCH_SHAPES)]
+    Fs = [p[0] for p in pairs]
+    Ms = [p[1] for p in pairs]
+    b = _lib.Batch(BATCH_SHAPES, window=WINDOW, grad_sigma=SIGMA)
+    cache = os.path.join(ROOT, "gpurun_out", "batch_tune.txt")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    tune_ms = b.tune(Fs, Ms, cache_path=cache, iters=3)
+    cfg = b.config()
+    for _ in range(a.warmup):
+        b.begin(Fs, Ms)
+        b.step(BATCH_ITERS, graph=True)
+        b.sync()
+    b.begin(Fs, Ms)
+    b.sync()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        b.begin(Fs, Ms)
+        b.step(BATCH_ITERS, graph=True)
+    b.sync()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    ntot = sum(int(np.prod(sh)) for sh in BATCH_SHAPES)
+    attempts = [b.pair(i).state()["attempts"] for i in range(len(BATCH_SHAPES))]
+    vox_att = sum(int(np.prod(sh)) * n for sh, n in zip(BATCH_SHAPES, attempts))
+    value = vox_att * a.steps / elapsed
+    per_attempt_s = elapsed / (a.steps * BATCH_ITERS)
+    achieved = attempt_bytes(4) * ntot / per_attempt_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_for("batch_attempt", "batch16_f32_w7"),
+                "kernel": "batch_attempt (one persistent launch per attempt)",
+                "algorithmic_bytes_per_launch": attempt_bytes(4) * ntot,
+                "mean_launch_ms": round(per_attempt_s * 1e3, 5),
+                "launches_timed": a.steps * BATCH_ITERS}
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(Fs[0].cpu().numpy(), Ms[0].cpu().numpy(),
+                           what="the smallest pair of the batch")
+    config = {"workload": "16 brain-like pairs (4x96^3, 4x128x160x128, 4x160x192x224, "
+                          "4x192x160x256), FP32, LNCC w=7, sigma_g=1, 150 attempts at "
+                          "full resolution, one persistent launch per attempt in a HIP "
+                          "graph, autotuned tiling",
+              "pairs": len(BATCH_SHAPES), "voxel_attempts_per_step": vox_att}
+    detail = {"tuned_config": cfg, "tune_ms_per_attempt": tune_ms,
+              "accepted_losses": [b.pair(i).state()["loss"] for i in range(len(BATCH_SHAPES))],
+              "kernel_source_sha": source_sha()}
+    return "f32", value, elapsed, config, roofline, cpu, detail
 
 
 def main():
@@ -105,89 +275,28 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("brain", "lung", "batch"), default="brain")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(the registration of one pair runs on one device).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-    from paper_2603_19371_amd import _lib, phantoms
-
-    ph = phantoms.brain(SHAPE, seed=0)
-    F = torch.from_numpy(ph.F).cuda()
-    M = torch.from_numpy(ph.M).cuda()
-    pyr = _lib.Pyramid(SHAPE, FACTORS, window=WINDOW, grad_sigma=SIGMA)
-    out = torch.empty((3,) + SHAPE, device="cuda")
-    for _ in range(a.warmup):
-        pyr.run(F, M, ITERS, lambda0=1.0, out=out)
-    torch.cuda.synchronize()
-
-    fine = pyr.level(len(FACTORS) - 1)
-    fine.profile_start(max_attempts=ITERS[-1] * a.steps, stride=1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        pyr.run(F, M, ITERS, lambda0=1.0, out=out)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = fine.profile_stop()
-
-    per_level = []
-    vox_att = 0
-    for l, f in enumerate(FACTORS):
-        st = pyr.level(l).state()
-        n = int(np.prod([s // f for s in SHAPE]))
-        per_level.append({"factor": f, "voxels": n, "attempts": int(st["attempts"]),
-                          "accepted_loss": st["loss"], "lambda": st["lambda_"]})
-        vox_att += n * int(st["attempts"])
-    elapsed = t1 - t0
-    value = vox_att * a.steps / elapsed
-
-    s = 4
-    nfine = int(np.prod(SHAPE))
-    kb = kernel_bytes(s)
-    dom = max((k for k in prof if prof[k]["count"]), key=lambda k: prof[k]["total_ms"])
-    avg_s = prof[dom]["avg_ms"] * 1e-3
-    achieved = kb[dom] * nfine / avg_s / 1e9
-    attempt_ms = sum(v["avg_ms"] for v in prof.values() if v["count"])
-    workload = "brain160x192x224_f32_w7"
-    traffic = traffic_for(dom, workload)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": dom,
-                "algorithmic_bytes_per_launch": kb[dom] * nfine,
-                "mean_launch_ms": round(prof[dom]["avg_ms"], 5),
-                "launches_timed": prof[dom]["count"]}
-
-    cpu = None
-    if not a.no_cpu_baseline:
-        cpu = cpu_baseline(ph)
-
+    run = {"brain": run_brain, "lung": run_lung, "batch": run_batch}[a.workload]
+    dtype, value, elapsed, config, roofline, cpu, detail = run(a)
     line = {
-        "metric": "voxel-attempts/s of the LM step (full coarse-to-fine registration)",
+        "metric": "voxel-attempts/s of the LM step (full coarse-to-fine registration)"
+                  if a.workload != "batch" else
+                  "voxel-attempts/s of the LM step (batched pairs)",
         "value": round(value, 1), "unit": "voxel-attempts/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(elapsed / a.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "brain-MRI-like phantom 160x192x224, FP32 images "
-                               "and field, LNCC w=7, sigma_g=1, pyramid 4x/2x/1x "
-                               "with 200/100/50 attempts, lambda0=1, x2/x0.5, tau=0",
-                   "pairs": 1, "voxel_attempts_per_step": vox_att},
+        "dtype": dtype, "data": "synthetic",
+        "config": config,
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "detail": {
-            "levels": per_level,
-            "fine_level_kernel_ms": {k: round(v["avg_ms"], 5) for k, v in prof.items()
-                                     if v["count"]},
-            "fine_level_attempt_ms": round(attempt_ms, 5),
-            "fine_level_voxel_attempts_per_s": round(nfine / (attempt_ms * 1e-3), 1),
-            "fine_level_attempt_algorithmic_frac": round(
-                attempt_bytes(s) * nfine / (attempt_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "kernel_source_sha": source_sha(),
-        },
+        "detail": detail,
     }
     print(json.dumps(line), flush=True)
 

@@ -348,9 +348,39 @@ def _profile_stop(h) -> dict:
 class LevelView:
     """Borrowed view of one pyramid level's context."""
 
-    def __init__(self, handle, shape):
+    def __init__(self, handle, shape, img_dtype=torch.float32):
         self._h = handle
         self.shape = shape
+        self.img_dtype = img_dtype
+
+    def _imgs(self, F, M):
+        return (_dev(F, self.shape, self.img_dtype, "fixed"),
+                _dev(M, self.shape, self.img_dtype, "moving"))
+
+    def begin(self, F, M, field=None, lambda0=1.0):
+        f, m = self._imgs(F, M)
+        u = _dev(field, (3,) + self.shape, torch.float32, "field") if field is not None \
+            else None
+        _check(lib().lmr_begin(self._h, f, m, u, float(lambda0)), "lmr_begin")
+
+    def step(self, F, M, n=1):
+        """Attempts on this level (images of this level's size)."""
+        f, m = self._imgs(F, M)
+        _check(lib().lmr_step(self._h, f, m, int(n)), "lmr_step")
+
+    def field(self):
+        """Copy of the accepted field (synchronises the context's stream, which
+        need not be torch's current one)."""
+        out = torch.empty((3,) + self.shape, device="cuda")
+        _check(lib().lmr_get_field(self._h, out.data_ptr()), "lmr_get_field")
+        _check(lib().lmr_get_state(self._h, C.byref(PairState())), "lmr_get_state")
+        return out
+
+    def folded_count(self, u=None):
+        up = _dev(u, (3,) + self.shape, torch.float32, "u") if u is not None else None
+        n = C.c_longlong()
+        _check(lib().lmr_folded_count(self._h, up, C.byref(n), None), "lmr_folded_count")
+        return n.value
 
     def state(self) -> dict:
         s = PairState()
@@ -395,7 +425,8 @@ class Pyramid:
         if not h:
             raise LmrError(f"no level {l}")
         f = self.factors[l]
-        return LevelView(C.c_void_p(h), tuple(s // f for s in self.shape))
+        return LevelView(C.c_void_p(h), tuple(s // f for s in self.shape),
+                         self.img_dtype if f == 1 else torch.float32)
 
     def run(self, F, M, iters, lambda0=1.0, decisions=None, out=None):
         f = _dev(F, self.shape, self.img_dtype, "fixed")
@@ -481,17 +512,11 @@ class Batch:
         h = lib().lmr_batch_pair(self._h, int(i))
         if not h:
             raise LmrError(f"no pair {i}")
-        return PairView(C.c_void_p(h), self.shapes[i])
+        return PairView(C.c_void_p(h), self.shapes[i], self.img_dtype)
 
 
 class PairView(LevelView):
     """Borrowed view of one pair of a batch."""
-
-    def field(self):
-        out = torch.empty((3,) + self.shape, device="cuda")
-        _check(lib().lmr_get_field(self._h, out.data_ptr()), "lmr_get_field")
-        _check(lib().lmr_get_state(self._h, C.byref(PairState())), "lmr_get_state")
-        return out
 
 
 def avgpool(img: torch.Tensor, f: int, stream=None) -> torch.Tensor:
