@@ -32,7 +32,6 @@ print a line of the same form:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -66,26 +65,26 @@ def attempt_bytes(s):
 
 
 def source_sha() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2603_19371_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2603_19371_amd.pmc_summary import source_sha as sha
+    return sha()
 
 
 def traffic_for(kernel: str, workload: str):
-    """HBM bytes per launch from profiles/<kernel>__<workload>.pmc.json, if the
-    counters were taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}__{workload}.pmc.json")
+    """HBM bytes per launch from profiles/<kernel>__<workload>.pmc.txt (written
+    by paper_2603_19371_amd.pmc_summary from rocprofv3 counters), if they were
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}__{workload}.pmc.txt")
     if not os.path.exists(path):
         return None
+    d = {}
     with open(path) as fh:
-        d = json.load(fh)
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                d[k.strip()] = v.strip()
     if d.get("source_sha") != source_sha():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return float(d["hbm_bytes_per_launch"])
 
 
 def cpu_baseline(F, M, attempts=2, what="the full-resolution level"):

@@ -368,12 +368,14 @@ class LevelView:
         f, m = self._imgs(F, M)
         _check(lib().lmr_step(self._h, f, m, int(n)), "lmr_step")
 
-    def field(self):
-        """Copy of the accepted field (synchronises the context's stream, which
-        need not be torch's current one)."""
+    def field(self, sync=True):
+        """Copy of the accepted field.  sync=True synchronises the context's
+        stream (which need not be torch's current one); sync=False only
+        enqueues the copy on it."""
         out = torch.empty((3,) + self.shape, device="cuda")
         _check(lib().lmr_get_field(self._h, out.data_ptr()), "lmr_get_field")
-        _check(lib().lmr_get_state(self._h, C.byref(PairState())), "lmr_get_state")
+        if sync:
+            _check(lib().lmr_get_state(self._h, C.byref(PairState())), "lmr_get_state")
         return out
 
     def folded_count(self, u=None):

@@ -17,6 +17,7 @@ namespace lmr {
 namespace {
 
 constexpr int kBX = 64, kBY = 4;
+constexpr int kUpdZ = 4;  // voxels per thread (along z) of the update kernel
 
 __device__ __forceinline__ bool voxel(const Geom& g, int& x, int& y, int& z, int& i) {
   x = blockIdx.x * kBX + threadIdx.x;
@@ -66,9 +67,10 @@ __global__ void __launch_bounds__(kBX* kBY)
     a.eps = eps;
     a.compositive = compositive;
   }
-  int x, y, z, i;
-  if (!voxel(g, x, y, z, i)) return;
-  update_voxel(M, g, a, x, y, z);
+  const int x = blockIdx.x * kBX + threadIdx.x;
+  const int y = blockIdx.y * kBY + threadIdx.y;
+  if (x >= g.nx || y >= g.ny) return;
+  update_voxels<T, kUpdZ>(M, g, a, x, y, blockIdx.z * kUpdZ);
 }
 
 constexpr int kDecideThreads = 256;
@@ -131,12 +133,13 @@ hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
   dim3 blk(kBX, kBY);
   const float rf = static_cast<float>(r), lf = static_cast<float>(lambda);
   const float eps = static_cast<float>(p.step_eps);
+  const dim3 grid((g.nx + kBX - 1) / kBX, (g.ny + kBY - 1) / kBY, (g.nz + kUpdZ - 1) / kUpdZ);
   if (t == LMR_BF16)
-    hipLaunchKernelGGL(k_update<uint16_t>, vox_grid(g), blk, 0, s,
+    hipLaunchKernelGGL(k_update<uint16_t>, grid, blk, 0, s,
                        static_cast<const uint16_t*>(M), g, st, G, U0, U1, u_in, u_out,
                        rf, lf, eps, p.compositive, Mw);
   else
-    hipLaunchKernelGGL(k_update<float>, vox_grid(g), blk, 0, s,
+    hipLaunchKernelGGL(k_update<float>, grid, blk, 0, s,
                        static_cast<const float*>(M), g, st, G, U0, U1, u_in, u_out, rf,
                        lf, eps, p.compositive, Mw);
   return hipGetLastError();

@@ -45,16 +45,16 @@ __device__ __forceinline__ float ldf(const uint16_t* p, int i) {
   return __uint_as_float(static_cast<uint32_t>(p[i]) << 16);
 }
 
-// Integer cell and fractional offset of the sample coordinate base + d.
-// base + d is formed in FP64, which is exact for an FP32 d and an integer
-// base, so the choice of cell does not depend on the rounding of a float sum.
-// Coordinates beyond +-1e9 (and NaN) are clamped far outside the volume.
+// Integer cell and fractional offset of the sample coordinate base + d, as
+// if base + d were formed exactly: floor(base + d) = base + floor(d) for an
+// integer base, and d - floor(d) is exact in FP32, so the choice of cell does
+// not depend on the rounding of a float sum.  Offsets beyond +-1e9 (and NaN)
+// are clamped far outside the volume.
 __device__ __forceinline__ void cell(int base, float d, int& i0, float& f) {
-  double p = static_cast<double>(base) + static_cast<double>(d);
-  p = fmin(fmax(p, -1e9), 1e9);
-  double fl = floor(p);
-  i0 = static_cast<int>(fl);
-  f = static_cast<float>(p - fl);
+  const float dc = fminf(fmaxf(d, -1e9f), 1e9f);
+  const float fl = floorf(dc);
+  i0 = base + static_cast<int>(fl);
+  f = dc - fl;
 }
 
 // The trilinear cell of the point (x+dx, y+dy, z+dz): lower corner, weights
@@ -187,26 +187,41 @@ __device__ __forceinline__ void bst(const RBuf& b, unsigned i, float v) {
 
 // The trilinear cell addressed through buffers.  Each corner coordinate is
 // clamped into the volume, so all eight loads are in range and issued
-// unconditionally; a corner that lies outside the volume along any axis is
-// then replaced by 0.  (Offsets are never formed by wrap-around: adjacent
-// loads may be fused into one wider access, which the hardware range-checks
-// as a whole.)
+// unconditionally; zero padding is applied through the weights instead: the
+// weight (and derivative sign) of a corner plane outside the volume is 0.
+// This gives the same sums, rounding included, as interpolating corners
+// replaced by 0.  (Offsets are never formed by wrap-around: adjacent loads
+// may be fused into one wider access, which the hardware range-checks as a
+// whole.)
 struct BCell {
-  float fx, fy, fz;
-  unsigned o[8];           // corner (i, j, k) at o[4k + 2j + i]
-  unsigned char m;         // bit 4k+2j+i: corner (i, j, k) inside the volume
+  unsigned o[8];            // corner (i, j, k) at o[4k + 2j + i]
+  float wx0, wx1, wy0, wy1, wz0, wz1;  // 1-f, f per axis; 0 outside
+  float sx0, sx1, sy0, sy1, sz0, sz1;  // -1, +1 per axis; 0 outside
 };
 
 __device__ __forceinline__ BCell make_bcell(const Geom& g, int x, int y, int z, float dx,
                                             float dy, float dz) {
   int x0, y0, z0;
-  BCell c;
-  cell(x, dx, x0, c.fx);
-  cell(y, dy, y0, c.fy);
-  cell(z, dz, z0, c.fz);
+  float fx, fy, fz;
+  cell(x, dx, x0, fx);
+  cell(y, dy, y0, fy);
+  cell(z, dz, z0, fz);
   const bool x0i = (unsigned)x0 < (unsigned)g.nx, x1i = (unsigned)(x0 + 1) < (unsigned)g.nx;
   const bool y0i = (unsigned)y0 < (unsigned)g.ny, y1i = (unsigned)(y0 + 1) < (unsigned)g.ny;
   const bool z0i = (unsigned)z0 < (unsigned)g.nz, z1i = (unsigned)(z0 + 1) < (unsigned)g.nz;
+  BCell c;
+  c.wx0 = x0i ? 1.0f - fx : 0.0f;
+  c.wx1 = x1i ? fx : 0.0f;
+  c.wy0 = y0i ? 1.0f - fy : 0.0f;
+  c.wy1 = y1i ? fy : 0.0f;
+  c.wz0 = z0i ? 1.0f - fz : 0.0f;
+  c.wz1 = z1i ? fz : 0.0f;
+  c.sx0 = x0i ? -1.0f : 0.0f;
+  c.sx1 = x1i ? 1.0f : 0.0f;
+  c.sy0 = y0i ? -1.0f : 0.0f;
+  c.sy1 = y1i ? 1.0f : 0.0f;
+  c.sz0 = z0i ? -1.0f : 0.0f;
+  c.sz1 = z1i ? 1.0f : 0.0f;
   const int xa = min(max(x0, 0), g.nx - 1), xb = min(max(x0 + 1, 0), g.nx - 1);
   const int ya = min(max(y0, 0), g.ny - 1), yb = min(max(y0 + 1, 0), g.ny - 1);
   const int za = min(max(z0, 0), g.nz - 1), zb = min(max(z0 + 1, 0), g.nz - 1);
@@ -220,14 +235,6 @@ __device__ __forceinline__ BCell make_bcell(const Geom& g, int x, int y, int z, 
   c.o[5] = r10 + xb;
   c.o[6] = r11 + xa;
   c.o[7] = r11 + xb;
-  c.m = 0;
-#pragma unroll
-  for (int k = 0; k < 2; ++k)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-        if ((i ? x1i : x0i) && (j ? y1i : y0i) && (k ? z1i : z0i)) c.m |= 1u << (4 * k + 2 * j + i);
   return c;
 }
 
@@ -235,18 +242,30 @@ template <typename T>
 __device__ __forceinline__ void bcorners(const RBuf& b, const Geom&, const BCell& c,
                                          float v[8]) {
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const float t = bld<T>(b, c.o[q]);
-    v[q] = (c.m >> q) & 1u ? t : 0.0f;
-  }
+  for (int q = 0; q < 8; ++q) v[q] = bld<T>(b, c.o[q]);
 }
 
-__device__ __forceinline__ float binterp(const BCell& b, const float v[8], float* grad) {
-  Cell c;
-  c.fx = b.fx;
-  c.fy = b.fy;
-  c.fz = b.fz;
-  return interp(c, v, grad);
+// Interpolated value; grad (may be null) receives the derivative of the
+// interpolant on the cell along x, y, z.
+__device__ __forceinline__ float binterp(const BCell& c, const float v[8], float* grad) {
+  const float c00 = lerp2(c.wx0, v[0], c.wx1, v[1]);
+  const float c01 = lerp2(c.wx0, v[2], c.wx1, v[3]);
+  const float c10 = lerp2(c.wx0, v[4], c.wx1, v[5]);
+  const float c11 = lerp2(c.wx0, v[6], c.wx1, v[7]);
+  const float c0 = lerp2(c.wy0, c00, c.wy1, c01);
+  const float c1 = lerp2(c.wy0, c10, c.wy1, c11);
+  if (grad) {
+    const float d00 = lerp2(c.sx0, v[0], c.sx1, v[1]);
+    const float d01 = lerp2(c.sx0, v[2], c.sx1, v[3]);
+    const float d10 = lerp2(c.sx0, v[4], c.sx1, v[5]);
+    const float d11 = lerp2(c.sx0, v[6], c.sx1, v[7]);
+    grad[0] = lerp2(c.wz0, lerp2(c.wy0, d00, c.wy1, d01), c.wz1,
+                    lerp2(c.wy0, d10, c.wy1, d11));
+    grad[1] = lerp2(c.wz0, lerp2(c.sy0, c00, c.sy1, c01), c.wz1,
+                    lerp2(c.sy0, c10, c.sy1, c11));
+    grad[2] = lerp2(c.sz0, c0, c.sz1, c1);
+  }
+  return lerp2(c.wz0, c0, c.wz1, c1);
 }
 
 // Bijective remap of a linear block index so that the blocks which the

@@ -170,24 +170,85 @@ def _first_reaching(losses, target):
     return None
 
 
-def evaluate(init: LearnedInit, seeds, max_attempts=50, tol=1e-3, fold_frac=1e-4,
-             fold_ref=None, log=print):
+def _start(init, pyr, F, M, schedule):
+    """Inference (init None: the identity instead) and every refinement stage
+    but the last: returns the field the last (full-resolution) stage begins
+    from.  schedule: (factor, attempts) stages, coarse to fine, the last at
+    factor 1; a factor-2 stage begins from the network's field itself (it is
+    on that grid)."""
+    half = tuple(s // 2 for s in F.shape)
+    if init is not None:
+        u = init.net.forward(F, M, pool=True)
+    else:
+        u = torch.zeros((3,) + half, device="cuda")
+    for f, n in schedule[:-1]:
+        if f != 2:
+            raise ValueError("refinement stages below full resolution run at factor 2")
+        lv = pyr.level(FACTORS.index(2))
+        Fp, Mp = _lib.avgpool(F, 2), _lib.avgpool(M, 2)
+        lv.begin(Fp, Mp, field=u, lambda0=1.0)
+        lv.step(Fp, Mp, n)
+        u = lv.field(sync=False)
+    return _lib.upsample_field(u)
+
+
+def _refine(init, pyr, fine, F, M, schedule, target):
+    """Tracked then timed run of start + full-resolution attempts until the
+    target; returns (losses, first attempt at target or None, folded count,
+    start ms, ms to the target or to the last attempt, begin loss)."""
+    max_attempts = schedule[-1][1]
+    u0 = _start(init, pyr, F, M, schedule)
+    fine.begin(F, M, field=u0, lambda0=1.0)
+    begin_loss = fine.state()["loss"]
+    losses = []
+    for _ in range(max_attempts):
+        fine.step(F, M, 1)
+        losses.append(fine.state()["loss"])
+        if losses[-1] <= target:
+            break
+    k = _first_reaching(losses, target)
+    folded = fine.folded_count()
+    torch.cuda.synchronize()
+    clk = _Clock()
+    c0 = clk.mark()
+    u0 = _start(init, pyr, F, M, schedule)
+    c1 = clk.mark()
+    fine.begin(F, M, field=u0, lambda0=1.0)
+    marks = []
+    for _ in range(len(losses)):
+        fine.step(F, M, 1)
+        marks.append(clk.mark())
+    torch.cuda.synchronize()
+    t_end = clk.ms(c0, marks[k if k is not None else -1])
+    return losses, k, folded, clk.ms(c0, c1), t_end, begin_loss
+
+
+def evaluate(init: LearnedInit, seeds, schedule=((1, 50),), tol=1e-3, fold_frac=1e-4,
+             ablation=True, log=print):
     """Time to the plain method's final LNCC (within tol): plain coarse-to-fine
-    LM from the identity vs prediction + LM refinement at full resolution.
+    LM from the identity vs prediction + LM refinement (`schedule`, ending
+    with at most schedule[-1][1] attempts at full resolution).  With
+    `ablation` the same schedule is also run from the identity (the network
+    replaced by a zero field), which separates what the network contributes
+    from what the schedule does.
 
     Each run is done twice: once reading the state after every attempt (which
     attempt first reaches the target; untimed), once timed with events after
     every attempt and no host reads; the runs are bitwise identical, so the
-    time to the target is the event time at that attempt."""
+    time to the target is the event time at that attempt.  A learned run that
+    misses the target, or folds more than the plain run's count + fold_frac N
+    voxels, falls back to the plain method and is charged both."""
     shape = init.shape
     N = int(np.prod(shape))
+    schedule = [tuple(st) for st in schedule]
+    if schedule[-1][0] != 1:
+        raise ValueError("the last refinement stage runs at full resolution")
     pyr = _lib.Pyramid(shape, FACTORS, window=WINDOW, grad_sigma=SIGMA)
     fine = pyr.level(len(FACTORS) - 1)
     coarse_iters = ITERS[:-1] + (0,)
     u = torch.empty((3,) + shape, device="cuda")
     rows = []
-    t_start = time.time()
-    last = t_start
+    last = time.time()
     for i, seed in enumerate(seeds):
         F, M, _ = phantoms_torch.brain(shape, seed=seed)
         # plain, tracked
@@ -212,61 +273,54 @@ def evaluate(init: LearnedInit, seeds, max_attempts=50, tol=1e-3, fold_frac=1e-4
         torch.cuda.synchronize()
         t_plain = clk.ms(c0, marks[k_plain])
         t_plain_full = clk.ms(c0, marks[-1])
-        # learned, tracked
-        u0 = init.predict(F, M)
-        fine.begin(F, M, field=u0, lambda0=1.0)
-        init_loss = fine.state()["loss"]
-        learned_losses = []
-        for _ in range(max_attempts):
-            fine.step(F, M, 1)
-            learned_losses.append(fine.state()["loss"])
-            if learned_losses[-1] <= target:
-                break
-        k_learned = _first_reaching(learned_losses, target)
-        learned_folded = fine.folded_count()
-        limit = (fold_ref if fold_ref is not None else plain_folded) + fold_frac * N
-        ok = k_learned is not None and learned_folded <= limit
-        # learned, timed
-        torch.cuda.synchronize()
-        clk = _Clock()
-        c0 = clk.mark()
-        u0 = init.predict(F, M)
-        c1 = clk.mark()
-        fine.begin(F, M, field=u0, lambda0=1.0)
-        marks = []
-        for _ in range(len(learned_losses)):
-            fine.step(F, M, 1)
-            marks.append(clk.mark())
-        torch.cuda.synchronize()
-        t_inf = clk.ms(c0, c1)
-        t_learned_run = clk.ms(c0, marks[-1])
-        t_learned = clk.ms(c0, marks[k_learned]) if ok else t_learned_run + t_plain
-        rows.append(dict(seed=int(seed), plain_final_loss=plain_final,
-                         plain_attempt_to_target=k_plain + 1, t_plain_ms=t_plain,
-                         t_plain_full_ms=t_plain_full, plain_folded=int(plain_folded),
-                         init_loss=init_loss, learned_final_loss=learned_losses[-1],
-                         learned_attempts=len(learned_losses),
-                         learned_attempt_to_target=(k_learned + 1) if k_learned is not None
-                         else None, learned_folded=int(learned_folded),
-                         t_inference_ms=t_inf, t_learned_ms=t_learned, fallback=not ok))
+        # the network's field alone
+        fine.begin(F, M, field=init.predict(F, M), lambda0=1.0)
+        net_loss = fine.state()["loss"]
+        fine.begin(F, M, lambda0=1.0)
+        identity_loss = fine.state()["loss"]
+        row = dict(seed=int(seed), plain_final_loss=plain_final,
+                   plain_attempt_to_target=k_plain + 1, t_plain_ms=t_plain,
+                   t_plain_full_ms=t_plain_full, plain_folded=int(plain_folded),
+                   identity_loss=identity_loss, net_loss=net_loss)
+        variants = [("learned", init)] + ([("ablation", None)] if ablation else [])
+        for tag, net in variants:
+            losses, k, folded, t_start, t_end, begin_loss = _refine(
+                net, pyr, fine, F, M, schedule, target)
+            ok = k is not None and folded <= plain_folded + fold_frac * N
+            row.update({f"{tag}_begin_loss": begin_loss,
+                        f"{tag}_final_loss": losses[-1],
+                        f"{tag}_attempts": len(losses),
+                        f"{tag}_attempt_to_target": (k + 1) if k is not None else None,
+                        f"{tag}_folded": int(folded),
+                        f"t_{tag}_start_ms": t_start,
+                        f"t_{tag}_ms": t_end if ok else t_end + t_plain,
+                        f"{tag}_fallback": not ok})
+        rows.append(row)
         if time.time() - last > 10 or i == len(seeds) - 1:
             last = time.time()
-            r = rows[-1]
-            log(f"[eval] {i + 1}/{len(seeds)} seed {seed}: plain {r['t_plain_ms']:.1f} ms "
-                f"learned {r['t_learned_ms']:.1f} ms (attempts {r['learned_attempts']}, "
-                f"fallback {r['fallback']})")
+            log(f"[eval] {i + 1}/{len(seeds)} seed {seed}: plain {row['t_plain_ms']:.1f} ms, "
+                f"learned {row['t_learned_ms']:.1f} ms (full-res attempts "
+                f"{row['learned_attempts']}, fallback {row['learned_fallback']})")
     tp = np.array([r["t_plain_ms"] for r in rows])
-    tl = np.array([r["t_learned_ms"] for r in rows])
-    summary = dict(
-        seeds=len(rows), tol=tol,
-        plain_ms_median=float(np.median(tp)), plain_ms_p90=float(np.percentile(tp, 90)),
-        learned_ms_median=float(np.median(tl)), learned_ms_p90=float(np.percentile(tl, 90)),
-        speedup_median=float(np.median(tp) / np.median(tl)),
-        fallback_rate=float(np.mean([r["fallback"] for r in rows])),
-        inference_ms_median=float(np.median([r["t_inference_ms"] for r in rows])),
-        learned_attempts_median=float(np.median([r["learned_attempts"] for r in rows])),
-        gate="per-seed plain run (oracle gate): target = plain final loss + tol; "
-             "folded count <= plain count + fold_frac N")
+    summary = dict(seeds=len(rows), tol=tol, schedule=schedule,
+                   plain_ms_median=float(np.median(tp)),
+                   plain_ms_p90=float(np.percentile(tp, 90)),
+                   identity_loss_median=float(np.median([r["identity_loss"] for r in rows])),
+                   net_loss_median=float(np.median([r["net_loss"] for r in rows])),
+                   plain_final_loss_median=float(np.median([r["plain_final_loss"]
+                                                            for r in rows])))
+    for tag, _ in [("learned", 0)] + ([("ablation", 0)] if ablation else []):
+        tl = np.array([r[f"t_{tag}_ms"] for r in rows])
+        summary.update({
+            f"{tag}_ms_median": float(np.median(tl)),
+            f"{tag}_ms_p90": float(np.percentile(tl, 90)),
+            f"{tag}_speedup_median": float(np.median(tp) / np.median(tl)),
+            f"{tag}_fallback_rate": float(np.mean([r[f"{tag}_fallback"] for r in rows])),
+            f"{tag}_attempts_median": float(np.median([r[f"{tag}_attempts"] for r in rows])),
+            f"{tag}_start_ms_median": float(np.median([r[f"t_{tag}_start_ms"]
+                                                       for r in rows]))})
+    summary["gate"] = ("per-seed plain run (oracle gate): target = plain final loss + tol; "
+                       "folded count <= plain count + fold_frac N")
     return summary, rows
 
 
@@ -284,7 +338,8 @@ def main(argv=None):
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
     e.add_argument("--seeds", default="5000:5200")
-    e.add_argument("--max-attempts", type=int, default=50)
+    e.add_argument("--schedule", default="1:50",
+                   help="refinement stages factor:attempts, coarse to fine, e.g. 2:20,1:40")
     e.add_argument("--out", required=True)
     e.add_argument("--shape", default="160,192,224")
     a = ap.parse_args(argv)
@@ -312,7 +367,8 @@ def main(argv=None):
     else:
         lo, hi = (int(x) for x in a.seeds.split(":"))
         init = LearnedInit(shape, params=np.load(a.weights))
-        summary, rows = evaluate(init, range(lo, hi), max_attempts=a.max_attempts, log=log)
+        sched = [tuple(int(v) for v in st.split(":")) for st in a.schedule.split(",")]
+        summary, rows = evaluate(init, range(lo, hi), schedule=sched, log=log)
         with open(a.out, "w") as fh:
             json.dump(dict(summary=summary, rows=rows), fh, indent=1)
         log(json.dumps(summary))

@@ -1,0 +1,121 @@
+"""Summaries of rocprofv3 HBM byte counters for one kernel of a workload.
+
+    python -m paper_2603_19371_amd.pmc_summary \\
+        --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \\
+        --copy-bytes 1073741824 --kernel k_update --grid 7864320 \\
+        --name update --workload brain160x192x224_f32_w7 --command "..." \\
+        [--out profiles/update__brain160x192x224_f32_w7.pmc.txt]
+
+Inputs are the counter-collection CSV files of four rocprofv3 --pmc runs: the
+workload with FETCH_SIZE, the workload with WRITE_SIZE, and the reference copy
+(paper_2603_19371_amd.calib) with each counter.  FETCH_SIZE and WRITE_SIZE
+are read in KiB per dispatch; each is scaled by (bytes the copy must move) /
+(counter of the copy dispatch), so that the kernel's figure is in HBM bytes.
+The dispatches of the kernel are those whose name contains --kernel and
+whose grid size (work-items) equals --grid.  The summary records the hash of
+the kernel sources it was taken on (bench.py uses it only while it matches).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import os
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+def source_sha() -> str:
+    """Hash of the library sources (the same as bench.py's)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _rows(path):
+    with open(path, newline="") as fh:
+        yield from csv.DictReader(fh)
+
+
+def counter_per_dispatch(path, counter, kernel=None, grid=None):
+    """Mean of `counter` over the selected dispatches (values summed over
+    the counter's instances within a dispatch)."""
+    per = {}
+    for r in _rows(path):
+        if r.get("Counter_Name") != counter:
+            continue
+        name = r.get("Kernel_Name", "")
+        if kernel and kernel not in name:
+            continue
+        if grid is not None and int(float(r.get("Grid_Size", "0"))) != grid:
+            continue
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    if not per:
+        raise SystemExit(f"no {counter} rows for kernel {kernel!r} grid {grid} in {path}")
+    return statistics.mean(per.values()), len(per)
+
+
+def copy_scale(path, counter, nbytes):
+    """bytes / counter for the largest dispatch of the reference copy."""
+    best = 0.0
+    per = {}
+    for r in _rows(path):
+        if r.get("Counter_Name") != counter:
+            continue
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    for v in per.values():
+        best = max(best, v)
+    if best <= 0:
+        raise SystemExit(f"no {counter} rows in {path}")
+    return nbytes / best, best
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    for k in ("fetch", "write", "copy-fetch", "copy-write", "kernel", "name", "workload",
+              "command"):
+        ap.add_argument("--" + k, required=True)
+    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--grid", type=int, required=True)
+    ap.add_argument("--out")
+    a = ap.parse_args()
+    f_kib, nf = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel, a.grid)
+    w_kib, nw = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel, a.grid)
+    sf, cf = copy_scale(a.copy_fetch, "FETCH_SIZE", a.copy_bytes)
+    sw, cw = copy_scale(a.copy_write, "WRITE_SIZE", a.copy_bytes)
+    hbm = f_kib * sf + w_kib * sw
+    out = a.out or os.path.join(ROOT, "profiles", f"{a.name}__{a.workload}.pmc.txt")
+    lines = [
+        f"# rocprofv3 HBM counters: kernel {a.kernel} (grid {a.grid} work-items), "
+        f"workload {a.workload}",
+        f"# command: {a.command}",
+        f"# reference: python -m paper_2603_19371_amd.calib (copy of {a.copy_bytes} bytes "
+        f"read + written)",
+        f"source_sha: {source_sha()}",
+        f"dispatches_fetch: {nf}",
+        f"dispatches_write: {nw}",
+        f"fetch_size_per_dispatch: {f_kib:.1f}",
+        f"write_size_per_dispatch: {w_kib:.1f}",
+        f"copy_fetch_size: {cf:.1f}",
+        f"copy_write_size: {cw:.1f}",
+        f"fetch_scale: {sf:.6g}",
+        f"write_scale: {sw:.6g}",
+        f"hbm_read_bytes_per_launch: {f_kib * sf:.0f}",
+        f"hbm_write_bytes_per_launch: {w_kib * sw:.0f}",
+        f"hbm_bytes_per_launch: {hbm:.0f}",
+    ]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()

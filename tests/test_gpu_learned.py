@@ -1,0 +1,47 @@
+"""What the trained initializer gains over the method without it, at a small
+scale that trains in seconds: brain-like pairs of 64x64x80 (network at
+32x32x40), 64 training pairs with converged plain-LM targets, 6 held-out
+pairs.  Refinement: 20 LM attempts at half resolution from the network's
+field, then at most 40 at full resolution until the plain method's final
+loss (within 1e-3) is reached."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SHAPE = (64, 64, 80)
+SCHEDULE = ((2, 20), (1, 40))
+
+
+@pytest.fixture(scope="module")
+def trained():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_2603_19371_amd import learned
+    data = learned.make_training_set(range(1000, 1064), shape=SHAPE, log=lambda m: None)
+    init = learned.LearnedInit(SHAPE, seed=0)
+    hist = learned.train(init.net, data, epochs=24, batch=4, lr=2e-3, log=lambda m: None)
+    return learned, init, data, hist
+
+
+def test_training_fits_the_converged_fields(trained):
+    learned, init, data, hist = trained
+    base = float((data["T"] * 0.5).square().mean())   # MSE of the zero field
+    print(f"\n[learned] epoch MSE {[round(h, 4) for h in hist]}, zero-field MSE {base:.4f}")
+    assert hist[-1] < 0.85 * base
+    assert hist[-1] < min(hist[:4])
+
+
+def test_network_field_and_refinement_beat_the_identity(trained):
+    learned, init, _, _ = trained
+    summary, rows = learned.evaluate(init, range(5000, 5006), schedule=SCHEDULE,
+                                     log=lambda m: None)
+    print(f"\n[learned] {summary}")
+    better = sum(r["net_loss"] < r["identity_loss"] for r in rows)
+    # the network's field alone is a better start than the identity
+    assert better >= 5, [(r["net_loss"], r["identity_loss"]) for r in rows]
+    # and the refinement from it reaches the plain method's final loss sooner
+    assert summary["learned_fallback_rate"] <= 1 / 6, summary
+    assert summary["learned_speedup_median"] > 1.5, summary
+    assert summary["learned_ms_median"] <= summary["ablation_ms_median"], summary
