@@ -208,14 +208,15 @@ class Context:
         self.params = params if params is not None else Params.make(**kw)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._h = _V()
+        self._destroy = lib().lmr_destroy
         code = LMR_BF16 if img_dtype == torch.bfloat16 else LMR_F32
         _check(lib().lmr_create(C.byref(self._h), *self.shape, code,
                                 C.byref(self.params), _stream_handle(self.stream)),
                "lmr_create")
 
     def close(self):
-        if self._h:
-            lib().lmr_destroy(self._h)
+        if getattr(self, "_h", None):
+            self._destroy(self._h)
             self._h = _V()
 
     __del__ = close
@@ -408,6 +409,7 @@ class Pyramid:
         self.params = params if params is not None else Params.make(**kw)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._h = _V()
+        self._destroy = lib().lmr_pyramid_destroy
         fa = (C.c_int * len(self.factors))(*self.factors)
         code = LMR_BF16 if img_dtype == torch.bfloat16 else LMR_F32
         _check(lib().lmr_pyramid_create(C.byref(self._h), *self.shape, code,
@@ -416,8 +418,8 @@ class Pyramid:
                "lmr_pyramid_create")
 
     def close(self):
-        if self._h:
-            lib().lmr_pyramid_destroy(self._h)
+        if getattr(self, "_h", None):
+            self._destroy(self._h)
             self._h = _V()
 
     __del__ = close
@@ -459,6 +461,7 @@ class Batch:
         self.img_dtype = img_dtype
         self.params = params if params is not None else Params.make(**kw)
         self._h = _V()
+        self._destroy = lib().lmr_batch_destroy
         flat = (C.c_int * (3 * len(self.shapes)))(*[s for sh in self.shapes for s in sh])
         code = LMR_BF16 if img_dtype == torch.bfloat16 else LMR_F32
         _check(lib().lmr_batch_create(C.byref(self._h), len(self.shapes), flat, code,
@@ -466,8 +469,8 @@ class Batch:
         self._keep = None
 
     def close(self):
-        if self._h:
-            lib().lmr_batch_destroy(self._h)
+        if getattr(self, "_h", None):
+            self._destroy(self._h)
             self._h = _V()
 
     __del__ = close
@@ -566,12 +569,13 @@ class UNet:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.n_params = unet_param_count()
         self._h = _V()
+        self._destroy = lib().lmr_unet_destroy
         _check(lib().lmr_unet_create(C.byref(self._h), *self.shape,
                                      _stream_handle(self.stream)), "lmr_unet_create")
 
     def close(self):
-        if self._h:
-            lib().lmr_unet_destroy(self._h)
+        if getattr(self, "_h", None):
+            self._destroy(self._h)
             self._h = _V()
 
     __del__ = close

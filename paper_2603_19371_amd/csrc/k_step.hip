@@ -17,7 +17,8 @@ namespace lmr {
 namespace {
 
 constexpr int kBX = 64, kBY = 4;
-constexpr int kUpdZ = 4;  // voxels per thread (along z) of the update kernel
+constexpr int kUpdZ = 1;  // voxels per thread (along z) of the update kernel (measured: 1 or 2
+                          // best; 4 loses occupancy)
 
 __device__ __forceinline__ bool voxel(const Geom& g, int& x, int& y, int& z, int& i) {
   x = blockIdx.x * kBX + threadIdx.x;
