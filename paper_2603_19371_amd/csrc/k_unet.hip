@@ -115,6 +115,82 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
   }
 }
 
+// The same convolution with the operands staged in LDS.  A block owns a
+// 16 x 16 (x, y) tile of output voxels in one z plane and 16 output
+// channels; per chunk of 16 input channels it stages the 3 x 18 x 18 input
+// halo and the chunk's 27 weight slices, then each wave runs the MFMAs of
+// four 16-voxel rows for all 27 taps from LDS, reusing each weight operand
+// across its four rows.  (The streamed form above reads both operands from
+// memory for every MFMA and is bound by the memory unit's per-instruction
+// cost.)
+constexpr int kCT = 16;            // tile edge (x and y)
+constexpr int kCH = kCT + 2;       // halo tile edge
+__global__ void __launch_bounds__(256) k_conv_tile(ConvArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t s_x[3][kCH][kCH][16];
+  __shared__ __attribute__((aligned(16))) uint16_t s_w[27][16][16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nco = a.cout_p / 16;
+  const int x0 = blockIdx.x * kCT, y0 = blockIdx.y * kCT;
+  const int z = blockIdx.z / nco, co0 = (blockIdx.z % nco) * 16;
+  const int m = lane & 15, kq = lane >> 4;
+  f4 acc[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int c0 = 0; c0 < a.cin_p; c0 += 16) {
+    __syncthreads();  // the previous chunk's operands are no longer read
+    // input halo: 3 x 18 x 18 voxels x 16 channels, 4 channels per item
+    for (int it = threadIdx.x; it < 3 * kCH * kCH * 4; it += 256) {
+      const int q = it & 3, p = it >> 2;
+      const int xx = p % kCH, yy = (p / kCH) % kCH, zz = p / (kCH * kCH);
+      const int gx = x0 + xx - 1, gy = y0 + yy - 1, gz = z + zz - 1;
+      const int ci = c0 + 4 * q;
+      s4 v = {0, 0, 0, 0};
+      if ((unsigned)gx < (unsigned)a.nx && (unsigned)gy < (unsigned)a.ny &&
+          (unsigned)gz < (unsigned)a.nz && ci < a.cin_valid)
+        v = *reinterpret_cast<const s4*>(
+            a.X + ((long long)(gz * a.ny + gy) * a.nx + gx) * a.ldx + ci);
+      *reinterpret_cast<s4*>(&s_x[zz][yy][xx][4 * q]) = v;
+    }
+    // weights of the chunk: 27 taps x 16 output x 16 input channels
+    for (int it = threadIdx.x; it < 27 * 16 * 4; it += 256) {
+      const int q = it & 3, co = (it >> 2) & 15, t = it >> 6;
+      *reinterpret_cast<s4*>(&s_w[t][co][4 * q]) = *reinterpret_cast<const s4*>(
+          a.W + ((long long)t * a.cout_p + co0 + co) * a.cin_p + c0 + 4 * q);
+    }
+    __syncthreads();
+#pragma unroll 3
+    for (int t = 0; t < 27; ++t) {
+      const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;  // halo coordinates
+      const s4 b = *reinterpret_cast<const s4*>(&s_w[t][m][4 * kq]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int yl = wv * 4 + r;
+        const s4 av = *reinterpret_cast<const s4*>(&s_x[dz][yl + dy][m + dx][4 * kq]);
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b, acc[r], 0, 0, 0);
+      }
+    }
+  }
+  // D[4 kq + j][n]: voxel x0 + 4 kq + j of row y0 + 4 wv + r, output channel co0 + n
+  const int co = co0 + m;
+  if (co >= a.cout) return;
+  const float bias = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int y = y0 + wv * 4 + r;
+    if (y >= a.ny) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int x = x0 + 4 * kq + j;
+      if (x >= a.nx) continue;
+      const long long v = (long long)(z * a.ny + y) * a.nx + x;
+      float o = acc[r][j] + bias;
+      if (a.relu) o = fmaxf(o, 0.0f);
+      if (a.Y) a.Y[v * a.ldy + co] = f2bf(o);
+      if (a.yf) a.yf[v * a.ldf + co] = o;
+    }
+  }
+}
+
 // Weight gradient, partial over a chunk of (z, y) rows.  One wave per
 // (chunk, 16 input channels, 16 output channels) keeps the 27 tap tiles in
 // registers: A[m][k] = X[voxel k shifted by tap][ci m], B[k][n] = dZ[voxel k][co n]
@@ -422,6 +498,11 @@ void wgrad_chunks(int cin_p, int cout_p, int nz, int ny, int& nchunks, int& rpc)
 }  // namespace
 
 hipError_t unet_conv(const ConvArgs& a, hipStream_t s) {
+  if (a.ldx % 4 == 0 && (reinterpret_cast<uintptr_t>(a.X) % 8) == 0) {
+    dim3 grid((a.nx + kCT - 1) / kCT, (a.ny + kCT - 1) / kCT, a.nz * (a.cout_p / 16));
+    hipLaunchKernelGGL(k_conv_tile, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   dim3 grid((a.nx + 63) / 64, a.ny, a.nz * (a.cout_p / 16));
   const bool k32 = a.cin_p % 32 == 0 && a.ldx % 8 == 0 && a.cin_valid % 8 == 0 &&
                    (reinterpret_cast<uintptr_t>(a.X) % 16) == 0;
