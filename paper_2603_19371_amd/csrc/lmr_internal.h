@@ -186,15 +186,24 @@ __device__ __forceinline__ void bst(const RBuf& b, unsigned i, float v) {
 }
 
 // The trilinear cell addressed through buffers.  Each corner coordinate is
-// clamped into the volume, so all eight loads are in range and issued
+// clamped into the volume, so all loads are in range and issued
 // unconditionally; zero padding is applied through the weights instead: the
 // weight (and derivative sign) of a corner plane outside the volume is 0.
 // This gives the same sums, rounding included, as interpolating corners
 // replaced by 0.  (Offsets are never formed by wrap-around: adjacent loads
 // may be fused into one wider access, which the hardware range-checks as a
 // whole.)
+//
+// A gather costs the address and data paths of the vector memory unit per
+// load instruction and lane, not per byte, so for FP32 volumes the two
+// corners of a row are read with one 8-byte load at x = clamp(x0, 0, nx-2):
+// corner x0 is its second element only when x0 = nx-1, corner x0+1 its first
+// only when x0 = -1 (any other out-of-row corner has weight 0).
 struct BCell {
-  unsigned o[8];            // corner (i, j, k) at o[4k + 2j + i]
+  unsigned r[4];            // element offset of the corner rows (j, k) at r[2k + j]
+  unsigned xa, xb;          // clamped x of corners 0 and 1
+  unsigned xc;              // start of the two-element row read (nx >= 2)
+  bool hi0, lo1;            // corner 0 from the pair's 2nd element, corner 1 from its 1st
   float wx0, wx1, wy0, wy1, wz0, wz1;  // 1-f, f per axis; 0 outside
   float sx0, sx1, sy0, sy1, sz0, sz1;  // -1, +1 per axis; 0 outside
 };
@@ -222,27 +231,45 @@ __device__ __forceinline__ BCell make_bcell(const Geom& g, int x, int y, int z, 
   c.sy1 = y1i ? 1.0f : 0.0f;
   c.sz0 = z0i ? -1.0f : 0.0f;
   c.sz1 = z1i ? 1.0f : 0.0f;
-  const int xa = min(max(x0, 0), g.nx - 1), xb = min(max(x0 + 1, 0), g.nx - 1);
+  c.xa = min(max(x0, 0), g.nx - 1);
+  c.xb = min(max(x0 + 1, 0), g.nx - 1);
+  c.xc = min(max(x0, 0), max(g.nx - 2, 0));
+  c.hi0 = x0 >= g.nx - 1;
+  c.lo1 = x0 < 0;
   const int ya = min(max(y0, 0), g.ny - 1), yb = min(max(y0 + 1, 0), g.ny - 1);
   const int za = min(max(z0, 0), g.nz - 1), zb = min(max(z0 + 1, 0), g.nz - 1);
-  const int r00 = (za * g.ny + ya) * g.nx, r01 = (za * g.ny + yb) * g.nx;
-  const int r10 = (zb * g.ny + ya) * g.nx, r11 = (zb * g.ny + yb) * g.nx;
-  c.o[0] = r00 + xa;
-  c.o[1] = r00 + xb;
-  c.o[2] = r01 + xa;
-  c.o[3] = r01 + xb;
-  c.o[4] = r10 + xa;
-  c.o[5] = r10 + xb;
-  c.o[6] = r11 + xa;
-  c.o[7] = r11 + xb;
+  c.r[0] = (za * g.ny + ya) * g.nx;
+  c.r[1] = (za * g.ny + yb) * g.nx;
+  c.r[2] = (zb * g.ny + ya) * g.nx;
+  c.r[3] = (zb * g.ny + yb) * g.nx;
   return c;
 }
 
+// Corner values v[4k + 2j + i] (i along x, j along y, k along z).
 template <typename T>
 __device__ __forceinline__ void bcorners(const RBuf& b, const Geom&, const BCell& c,
                                          float v[8]) {
 #pragma unroll
-  for (int q = 0; q < 8; ++q) v[q] = bld<T>(b, c.o[q]);
+  for (int q = 0; q < 4; ++q) {
+    v[2 * q] = bld<T>(b, c.r[q] + c.xa);
+    v[2 * q + 1] = bld<T>(b, c.r[q] + c.xb);
+  }
+}
+template <>
+__device__ __forceinline__ void bcorners<float>(const RBuf& b, const Geom& g, const BCell& c,
+                                                float v[8]) {
+  if (g.nx < 2) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[2 * q] = v[2 * q + 1] = bld<float>(b, c.r[q] + c.xa);
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const auto p = __builtin_amdgcn_raw_buffer_load_b64(b.r, (c.r[q] + c.xc) * 4u, 0, 0);
+    const float lo = __uint_as_float(p[0]), hi = __uint_as_float(p[1]);
+    v[2 * q] = c.hi0 ? hi : lo;
+    v[2 * q + 1] = c.lo1 ? lo : hi;
+  }
 }
 
 // Interpolated value; grad (may be null) receives the derivative of the

@@ -1,6 +1,10 @@
-"""Summaries of rocprofv3 HBM byte counters for one kernel of a workload.
+"""Summaries of rocprofv3 output: HBM byte counters of one kernel, and
+kernel-trace durations per kernel and grid size.
 
-    python -m paper_2603_19371_amd.pmc_summary \\
+    python -m paper_2603_19371_amd.pmc_summary trace --trace T.csv \\
+        --workload brain160x192x224_f32_w7 --command "..." [--out F.txt]
+
+    python -m paper_2603_19371_amd.pmc_summary counters \\
         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \\
         --copy-bytes 1073741824 --kernel k_update --grid 7864320 \\
         --name update --workload brain160x192x224_f32_w7 --command "..." \\
@@ -78,15 +82,52 @@ def copy_scale(path, counter, nbytes):
     return nbytes / best, best
 
 
+def _short(name: str) -> str:
+    n = name.replace("(anonymous namespace)::", "").replace("lmr::", "")
+    n = n.replace("void ", "")
+    return n.split("(")[0]
+
+
+def trace_summary(a):
+    """Per (kernel, grid size): dispatches, mean / min / max duration."""
+    per = {}
+    for r in _rows(a.trace):
+        grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        per.setdefault((_short(r["Kernel_Name"]), grid), []).append(d)
+    total = sum(sum(v) for v in per.values())
+    lines = [f"# rocprofv3 kernel trace, workload {a.workload}",
+             f"# command: {a.command}",
+             "# kernel | grid (work-items) | dispatches | mean us | min us | max us | "
+             "share of kernel time"]
+    for (k, grid), v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{k} | {grid} | {len(v)} | {statistics.mean(v):.2f} | {min(v):.2f} | "
+                     f"{max(v):.2f} | {100 * sum(v) / total:.1f}%")
+    lines.append(f"# total kernel time {total * 1e-3:.2f} ms")
+    out = a.out or os.path.join(ROOT, "profiles", f"kernels__{a.workload}.txt")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    for k in ("trace", "workload", "command"):
+        t.add_argument("--" + k, required=True)
+    t.add_argument("--out")
+    c = sub.add_parser("counters")
     for k in ("fetch", "write", "copy-fetch", "copy-write", "kernel", "name", "workload",
               "command"):
-        ap.add_argument("--" + k, required=True)
-    ap.add_argument("--copy-bytes", type=int, required=True)
-    ap.add_argument("--grid", type=int, required=True)
-    ap.add_argument("--out")
+        c.add_argument("--" + k, required=True)
+    c.add_argument("--copy-bytes", type=int, required=True)
+    c.add_argument("--grid", type=int, required=True)
+    c.add_argument("--out")
     a = ap.parse_args()
+    if a.cmd == "trace":
+        trace_summary(a)
+        return
     f_kib, nf = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel, a.grid)
     w_kib, nw = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel, a.grid)
     sf, cf = copy_scale(a.copy_fetch, "FETCH_SIZE", a.copy_bytes)
