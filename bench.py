@@ -82,7 +82,9 @@ def traffic_for(kernel: str, workload: str):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 d[k.strip()] = v.strip()
-    if d.get("source_sha") != source_sha():
+    from paper_2603_19371_amd.pmc_summary import source_sha as sha
+    files = d.get("source_files", "").split()
+    if not files or d.get("source_sha") != sha(files):
         return None
     return float(d["hbm_bytes_per_launch"])
 

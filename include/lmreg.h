@@ -231,6 +231,13 @@ lmr_status lmr_pyramid_create(lmr_pyramid** out, int nz, int ny, int nx,
 lmr_status lmr_pyramid_run(lmr_pyramid* pyr, const void* fixed, const void* moving,
                            const int* iters, double lambda0, const int* decisions,
                            float* field_out);
+/* Automatic attempts of a level run as one HIP graph launch per level
+ * (captured on first use for the given images and attempt count, on a
+ * private stream, and replayed on the pyramid's stream; the images must stay
+ * at the same addresses for a replay to apply).  enable = 0 enqueues the
+ * attempts one kernel at a time instead.  Default: enabled.  Forced decisions
+ * and levels whose kernel timing is open always run eagerly. */
+lmr_status lmr_pyramid_use_graphs(lmr_pyramid* pyr, int enable);
 /* The context of level l (borrowed; valid until lmr_pyramid_destroy). */
 lmr_ctx* lmr_pyramid_level(lmr_pyramid* pyr, int level);
 void lmr_pyramid_destroy(lmr_pyramid* pyr);

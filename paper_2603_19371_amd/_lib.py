@@ -115,6 +115,7 @@ def lib() -> C.CDLL:
                                      _V]),
             "lmr_pyramid_level": (_V, [_V, _I]),
             "lmr_pyramid_destroy": (None, [_V]),
+            "lmr_pyramid_use_graphs": (_I, [_V, _I]),
             "lmr_batch_create": (_I, [C.POINTER(_V), _I, C.POINTER(_I), _I,
                                       C.POINTER(Params)]),
             "lmr_batch_begin": (_I, [_V, C.POINTER(_V), C.POINTER(_V),
@@ -157,7 +158,7 @@ def exported_symbols():
             "lmr_set_state", "lmr_kernel_name", "lmr_profile_start",
             "lmr_profile_stop", "lmr_avgpool", "lmr_upsample_field",
             "lmr_pyramid_create", "lmr_pyramid_run", "lmr_pyramid_level",
-            "lmr_pyramid_destroy", "lmr_folded_count", "lmr_batch_create",
+            "lmr_pyramid_destroy", "lmr_pyramid_use_graphs", "lmr_folded_count", "lmr_batch_create",
             "lmr_batch_begin", "lmr_batch_step", "lmr_batch_sync", "lmr_batch_pair",
             "lmr_batch_set_config", "lmr_batch_get_config", "lmr_batch_tune",
             "lmr_batch_destroy", "lmr_unet_param_count", "lmr_unet_layer_info",
@@ -423,6 +424,10 @@ class Pyramid:
             self._h = _V()
 
     __del__ = close
+
+    def use_graphs(self, enable: bool):
+        _check(lib().lmr_pyramid_use_graphs(self._h, int(bool(enable))),
+               "lmr_pyramid_use_graphs")
 
     def level(self, l) -> LevelView:
         h = lib().lmr_pyramid_level(self._h, int(l))

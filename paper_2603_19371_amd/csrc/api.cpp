@@ -5,7 +5,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "ctx.h"
@@ -462,15 +464,66 @@ struct lmr_pyramid {
   float* Ml[8];   // pooled moving image
   float* ul[8];   // field handed to level l
   void* arena;
+  // HIP graphs of the attempt sequences, keyed by (level, images, attempts);
+  // captured on a private stream, launched on the pyramid's stream
+  bool use_graphs = true;
+  hipStream_t cap = nullptr;
+  std::map<std::tuple<int, const void*, const void*, int>, hipGraphExec_t> graphs;
 };
+
+namespace {
+
+void drop_graphs(lmr_pyramid* y) {
+  for (auto& kv : y->graphs) (void)hipGraphExecDestroy(kv.second);
+  y->graphs.clear();
+}
+
+// n automatic attempts of level l as one graph launch on the pyramid's stream.
+lmr_status step_graph(lmr_pyramid* y, int l, const void* Fl, const void* Ml, int n) {
+  lmr_ctx* c = y->lv[l];
+  const auto key = std::make_tuple(l, Fl, Ml, n);
+  auto it = y->graphs.find(key);
+  if (it == y->graphs.end()) {
+    if (!y->cap) LMR_HIP(hipStreamCreateWithFlags(&y->cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const hipStream_t own = c->stream;
+    c->stream = y->cap;
+    hipError_t e = hipStreamBeginCapture(y->cap, hipStreamCaptureModeThreadLocal);
+    lmr_status st = e == hipSuccess ? lmr_step(c, Fl, Ml, n) : LMR_OK;
+    if (e == hipSuccess) e = hipStreamEndCapture(y->cap, &graph);
+    c->stream = own;
+    if (st != LMR_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    LMR_HIP(e);
+    it = y->graphs.emplace(key, exec).first;
+  }
+  LMR_HIP(hipGraphLaunch(it->second, y->stream));
+  return LMR_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
 void lmr_pyramid_destroy(lmr_pyramid* y) {
   if (!y) return;
+  (void)hipStreamSynchronize(y->stream);
+  drop_graphs(y);
+  if (y->cap) (void)hipStreamDestroy(y->cap);
   for (int l = 0; l < y->nlevels; ++l) lmr_destroy(y->lv[l]);
   (void)hipFree(y->arena);
   delete y;
+}
+
+lmr_status lmr_pyramid_use_graphs(lmr_pyramid* y, int enable) {
+  if (!y) return LMR_EINVAL;
+  y->use_graphs = enable != 0;
+  return LMR_OK;
 }
 
 lmr_status lmr_pyramid_create(lmr_pyramid** out, int nz, int ny, int nx, lmr_dtype img,
@@ -561,7 +614,12 @@ lmr_status lmr_pyramid_run(lmr_pyramid* y, const void* F, const void* M,
     }
     lmr_status st = lmr_begin(c, Fl, Ml, u0, lambda0);
     if (st != LMR_OK) return st;
-    st = d ? lmr_step_forced(c, Fl, Ml, d, iters[l]) : lmr_step(c, Fl, Ml, iters[l]);
+    if (d)
+      st = lmr_step_forced(c, Fl, Ml, d, iters[l]);
+    else if (y->use_graphs && !c->prof.on && iters[l] > 0)
+      st = step_graph(y, l, Fl, Ml, iters[l]);
+    else
+      st = lmr_step(c, Fl, Ml, iters[l]);
     if (st != LMR_OK) return st;
     if (d) d += iters[l];
   }

@@ -31,14 +31,30 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 
 
-def source_sha() -> str:
-    """Hash of the library sources (the same as bench.py's)."""
+# The sources each timed kernel is built from (the counters of a kernel stay
+# valid while these files are unchanged).
+KERNEL_SOURCES = {
+    "update": ["k_step.hip", "update.h", "lmr_internal.h"],
+    "lncc_fwd": ["k_stencil.hip", "stencil.h", "lmr_internal.h"],
+    "lncc_bwd": ["k_stencil.hip", "stencil.h", "lmr_internal.h"],
+    "smooth": ["k_stencil.hip", "stencil.h", "lmr_internal.h"],
+}
+
+
+def source_files(kernel: str | None = None):
+    csrc = os.path.join(HERE, "csrc")
+    if kernel in KERNEL_SOURCES:
+        return list(KERNEL_SOURCES[kernel])
+    return sorted(n for n in os.listdir(csrc) if n.endswith((".hip", ".h", ".cpp")))
+
+
+def source_sha(files=None) -> str:
+    """Hash of the given library sources (default: all of them)."""
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(fh.read())
+    for name in files if files is not None else source_files():
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -140,7 +156,8 @@ def main():
         f"# command: {a.command}",
         f"# reference: python -m paper_2603_19371_amd.calib (copy of {a.copy_bytes} bytes "
         f"read + written)",
-        f"source_sha: {source_sha()}",
+        f"source_files: {' '.join(source_files(a.name))}",
+        f"source_sha: {source_sha(source_files(a.name))}",
         f"dispatches_fetch: {nf}",
         f"dispatches_write: {nw}",
         f"fetch_size_per_dispatch: {f_kib:.1f}",

@@ -62,6 +62,26 @@ def test_pyramid_run_with_oracle_decisions(L, orc):
         assert pyr.level(l).state()["attempts"] == n
 
 
+def test_pyramid_graph_replays_match_eager_runs(L):
+    """The attempts of each level as one replayed HIP graph give the same
+    fields and states, bit for bit, as the kernel-by-kernel enqueue, over
+    repeated runs with other device work in between."""
+    from paper_2603_19371_amd import phantoms
+    ph = phantoms.brain((32, 40, 48), seed=4)
+    F, M = dev(ph.F), dev(ph.M)
+    iters = [12, 8, 5]
+    eager = L.Pyramid(ph.F.shape, (4, 2, 1), window=5)
+    eager.use_graphs(False)
+    ref = host(eager.run(F, M, iters))
+    ref_states = [eager.level(l).state() for l in range(3)]
+    graph = L.Pyramid(ph.F.shape, (4, 2, 1), window=5)
+    for rep in range(3):
+        out = graph.run(F, M, iters)
+        _ = (torch.ones(1000, device="cuda") * rep).sum().item()
+        assert np.array_equal(host(out), ref), rep
+        assert [graph.level(l).state() for l in range(3)] == ref_states, rep
+
+
 @pytest.mark.parametrize("shape", [(9, 10, 11), (20, 37, 70), (1, 16, 24)])
 def test_folded_count_is_bit_exact(L, orc, shape):
     """The count is an integer decided in FP64 with the oracle's operation
