@@ -234,7 +234,7 @@ def test_one_attempt_field_within_1e4(L, orc):
     assert abs(st["loss"] - pr.state.loss) < 1e-6
 
 
-def _teacher_forced(L, orc, F_or, M_or, F_gpu, M_gpu, img_dtype, n, refs):
+def _teacher_forced(L, orc, F_or, M_or, F_gpu, M_gpu, img_dtype, n, refs, window=5):
     """Runs the oracle's own config-1 trajectory (automatic decisions) and, at
     every attempt t, restarts the GPU from the oracle's accepted state: the
     field rounded to FP32 (the library's storage), lambda and the loss
@@ -243,9 +243,9 @@ def _teacher_forced(L, orc, F_or, M_or, F_gpu, M_gpu, img_dtype, n, refs):
     field.  ``refs`` lists (name, F, M, tol) oracle references evaluated on
     the same state.  Returns the per-attempt errors of every reference and
     the worst candidate-loss error against the first reference."""
-    p = orc.Params(window=5)
+    p = orc.Params(window=window)
     traj = orc.Pair(F_or, M_or, p).begin(lambda0=1.0)
-    ctx = L.Context(F_or.shape, img_dtype=img_dtype, window=5)
+    ctx = L.Context(F_or.shape, img_dtype=img_dtype, window=window)
     errs = {name: [] for name, *_ in refs}
     worst_loss = 0.0
     for t in range(n):
@@ -300,6 +300,36 @@ def test_teacher_forced_bf16_images(L, orc):
                              ("fp32-images", ph.F, ph.M, 5e-3)])
     assert max(errs["bf16-images"]) < 1e-4
     assert errs["fp32-images"][0] < 5e-3
+
+
+def test_lung_precision_form(L, orc):
+    """Precision form on a lung-CT-like pair (64^3, w = 7): BF16 images with
+    the FP32 field and the FP64 loss reduction.  Implementation: every
+    attempt of the oracle's trajectory restarted from the oracle's state
+    matches the oracle on the same BF16 values within 1e-4.  Precision
+    effect: the first attempt is within 5e-3 of the FP32-image oracle, and a
+    free two-level run (2x/1x, 20/10 attempts) ends within 2e-3 of the loss
+    of the FP32-image GPU run."""
+    from paper_2603_19371_amd.phantoms import bf16_to_f32, lung, to_bf16_rne
+    ph = lung((64, 64, 64), seed=2)
+    Fr, Mr = bf16_to_f32(to_bf16_rne(ph.F)), bf16_to_f32(to_bf16_rne(ph.M))
+    errs, _ = _teacher_forced(
+        L, orc, ph.F, ph.M, dev(Fr, torch.bfloat16), dev(Mr, torch.bfloat16),
+        torch.bfloat16, 10, [("lung bf16-images", Fr, Mr, 1e-4),
+                             ("lung fp32-images", ph.F, ph.M, 5e-3)], window=7)
+    assert max(errs["lung bf16-images"]) < 1e-4
+    assert errs["lung fp32-images"][0] < 5e-3
+    runs = {}
+    for name, F, M, dt in (("bf16", Fr, Mr, torch.bfloat16), ("fp32", ph.F, ph.M,
+                                                              torch.float32)):
+        pyr = L.Pyramid(ph.F.shape, (2, 1), img_dtype=dt, window=7)
+        u = host(pyr.run(dev(F, dt), dev(M, dt), [20, 10]))
+        runs[name] = (u, pyr.level(1).state()["loss"])
+    dL = abs(runs["bf16"][1] - runs["fp32"][1])
+    du = float(np.abs(runs["bf16"][0] - runs["fp32"][0]).max())
+    print(f"[lung precision] final loss bf16 {runs['bf16'][1]:.6f} fp32 "
+          f"{runs['fp32'][1]:.6f} |dL| {dL:.2e}; field max|diff| {du:.3e}", flush=True)
+    assert dL < 2e-3, dL
 
 
 def test_checkpoint_resume_is_bitwise(L):
