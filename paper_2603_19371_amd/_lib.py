@@ -218,7 +218,7 @@ class Context:
     def close(self):
         if getattr(self, "_h", None):
             self._destroy(self._h)
-            self._h = _V()
+            self._h = None  # (module globals may be gone at interpreter exit)
 
     __del__ = close
 
@@ -421,7 +421,7 @@ class Pyramid:
     def close(self):
         if getattr(self, "_h", None):
             self._destroy(self._h)
-            self._h = _V()
+            self._h = None  # (module globals may be gone at interpreter exit)
 
     __del__ = close
 
@@ -476,7 +476,7 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             self._destroy(self._h)
-            self._h = _V()
+            self._h = None  # (module globals may be gone at interpreter exit)
 
     __del__ = close
 
@@ -581,7 +581,7 @@ class UNet:
     def close(self):
         if getattr(self, "_h", None):
             self._destroy(self._h)
-            self._h = _V()
+            self._h = None  # (module globals may be gone at interpreter exit)
 
     __del__ = close
 

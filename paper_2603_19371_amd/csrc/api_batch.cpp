@@ -4,6 +4,7 @@
 // chosen by a measuring autotuner whose choices are cached in a text file.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stddef.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -64,6 +65,9 @@ lmr_status layout(lmr_batch* b) {
   b->n_tiles = tiles;
   LMR_HIP(hipMemcpyAsync(b->dev_pairs, b->host.data(), sizeof(BatchPair) * b->npairs,
                          hipMemcpyHostToDevice, b->stream));
+  // the barrier counters count arrivals of one grid size: start them over
+  // (the error flag stays until lmr_batch_sync reports it)
+  LMR_HIP(hipMemsetAsync(b->ctl, 0, offsetof(BatchCtl, error), b->stream));
   drop_graphs(b);
   return LMR_OK;
 }
@@ -242,7 +246,7 @@ lmr_status lmr_batch_sync(lmr_batch* b) {
   LMR_HIP(hipStreamSynchronize(b->stream));
   BatchCtl h;
   LMR_HIP(hipMemcpy(&h, b->ctl, sizeof h, hipMemcpyDeviceToHost));
-  if (h.error) {
+  if (h.error.v) {
     // clear the flag so that the batch can be used again
     LMR_HIP(hipMemset(b->ctl, 0, sizeof(BatchCtl)));
     return LMR_EHIP;

@@ -26,37 +26,50 @@ namespace {
 constexpr int kTY = 8;
 constexpr int kNT = kTX * kTY;
 
-// Grid-wide barrier among `nblocks` co-resident blocks.  A wait longer than
-// `timeout` ticks of the device's constant-rate wall clock records an error.
-// Returns false when this wait timed out or another block reported one.
+// Grid-wide barrier among `nblocks` co-resident blocks (two-level arrival on
+// monotonic counters, see BatchCtl).  A wait longer than `timeout` ticks of
+// the device's constant-rate wall clock records an error.  Returns false when
+// this wait timed out or another block reported one.
 __device__ bool grid_sync(BatchCtl* ctl, unsigned nblocks, unsigned long long timeout) {
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned g0 = __hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();  // this block's results become visible device-wide
-    const unsigned arrived = atomicAdd(&ctl->count, 1u) + 1u;
-    int good = 1;
-    if (arrived == nblocks) {
-      __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
-      __hip_atomic_fetch_add(&ctl->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      const unsigned long long t0 = wall_clock64();
-      while (__hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ==
-             g0) {
-        if (wall_clock64() - t0 > timeout ||
-            __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          good = 0;
-          atomicExch(&ctl->error, 1);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
+    // release: this block's results are written back to where blocks on the
+    // other chiplets read them, before its arrival is counted
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned grp = blockIdx.x % kBarGroups;
+    const unsigned long long in_grp = (nblocks + kBarGroups - 1 - grp) / kBarGroups;
+    const unsigned long long ngrp = nblocks < (unsigned)kBarGroups ? nblocks : kBarGroups;
+    const unsigned long long a = atomicAdd(&ctl->group[grp].v, 1ull);
+    const unsigned long long epoch = a / in_grp;  // barriers completed before this one
+    bool release = false;
+    if ((a + 1) % in_grp == 0) {
+      const unsigned long long t = atomicAdd(&ctl->top.v, 1ull);
+      if ((t + 1) % ngrp == 0) {
+        __hip_atomic_fetch_add(&ctl->gen.v, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        release = true;
       }
     }
-    __threadfence();  // results of the other blocks are visible here
-    ok = good && __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED,
+    int good = 1;
+    if (!release) {
+      const unsigned long long t0 = wall_clock64();
+      // relaxed polls (an acquire per poll would invalidate this chiplet's L2
+      // under the working blocks every time); the fence below acquires once
+      while (__hip_atomic_load(&ctl->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <=
+             epoch) {
+        if (wall_clock64() - t0 > timeout ||
+            __hip_atomic_load(&ctl->error.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          good = 0;
+          atomicExch(&ctl->error.v, 1ull);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(4);
+      }
+    }
+    // acquire: stale lines of this chiplet's caches are dropped, so the
+    // results of the other blocks are read from memory
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ok = good && __hip_atomic_load(&ctl->error.v, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT) == 0;
   }
   __syncthreads();
@@ -85,7 +98,7 @@ __global__ void __launch_bounds__(kNT)
                     unsigned long long timeout) {
   const int nb = gridDim.x;
   // after a barrier timeout every later launch returns at once
-  if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  if (__hip_atomic_load(&ctl->error.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
 
   // P1: closed form, compositive integration, candidate warp
   for (int it = blockIdx.x; it < n_vox_items; it += nb) {

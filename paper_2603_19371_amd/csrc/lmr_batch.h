@@ -28,12 +28,25 @@ struct BatchPair {
   float gw[16];      // Gaussian taps, 2R+1 <= 9 used
 };
 
-// Grid-barrier state and the timeout flag of the persistent kernel.
+// Grid-barrier state and the timeout flag of the persistent kernel.  Blocks
+// arrive on one of kBarGroups group counters (block id modulo the group
+// count, one cache line each); the last arrival of a group arrives on the top
+// counter, and the last of those releases everyone by raising the number of
+// completed barriers `gen`, which lives on its own line so that the waiting
+// blocks' polls do not contend with the arrivals.  The counters only grow
+// (64 bits, never reset inside a kernel) and are touched by atomic
+// read-modify-writes only: a block learns from its own arrival which barrier
+// it is at, and no plain store to a counter has to be ordered against the
+// atomics of blocks on other chiplets.
+constexpr int kBarGroups = 8;
 struct BatchCtl {
-  unsigned count;
-  unsigned gen;
-  int error;
-  int pad_;
+  struct alignas(128) Line {
+    unsigned long long v;
+  };
+  Line group[kBarGroups];
+  Line top;
+  Line gen;
+  Line error;
 };
 
 int batch_tile_rows();
