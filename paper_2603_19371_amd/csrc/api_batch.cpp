@@ -167,9 +167,9 @@ lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes, lmr_
     lmr_status st = lmr_create(&b->ctx[i], nz, ny, nx, img, p, b->stream);
     if (st != LMR_OK) return fail(st);
     lmr_ctx* c = b->ctx[i];
-    // partial slots for the largest tile count any tuning can produce (cz >= 4)
+    // partial slots for the largest tile count any tuning can produce (cz >= 2)
     const int ty = batch_tile_rows();
-    const size_t maxt = (size_t)((nx + kTX - 1) / kTX) * ((ny + ty - 1) / ty) * ((nz + 3) / 4);
+    const size_t maxt = (size_t)((nx + kTX - 1) / kTX) * ((ny + ty - 1) / ty) * ((nz + 1) / 2);
     if (hipMalloc(&b->partials[i], sizeof(double) * maxt) != hipSuccess)
       return fail(LMR_ENOMEM);
     BatchPair& P = b->host[i];

@@ -151,6 +151,8 @@ __device__ __forceinline__ float trilinear(const T* __restrict__ V, const Geom& 
 // no branch and can never fault.  Channels hold fewer than 2^30 voxels.
 constexpr int kBufDword3 = 0x00020000;  // raw 32-bit access on gfx9-class GPUs
 constexpr unsigned kFarOffset = 0xFFFFFFF0u;  // always beyond num_records
+// element index whose 4-byte offset lies beyond any channel (< 2^30 voxels)
+constexpr unsigned kFarIndex = 0x3FFFFFFFu;
 
 struct RBuf {
   __amdgpu_buffer_rsrc_t r;

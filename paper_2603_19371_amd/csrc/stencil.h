@@ -28,13 +28,13 @@
 namespace lmr {
 
 constexpr int kTX = 32;
-// element index whose byte offset lies beyond any channel (< 2^30 voxels)
-constexpr unsigned kFarIndex = 0x3FFFFFFFu;
 
 struct Tiling {
   int ty, tiles_x, tiles_y, nchunks, cz;
   __host__ __device__ int tiles() const { return tiles_x * tiles_y * nchunks; }
 };
+
+constexpr int kMinTiles = 256;  // one tile per CU
 
 // z-chunk: long enough that the 2R halo planes of a chunk stay a small
 // fraction when the volume is large, short enough that small volumes still
@@ -49,7 +49,10 @@ __host__ __device__ inline Tiling make_tiling(int nz, int ny, int nx, int ty,
   const int want = (target_tiles + cols - 1) / cols;
   int cz = (nz + want - 1) / want;
   if (cols * ((nz + min_cz - 1) / min_cz) >= target_tiles / 2 && cz < min_cz) cz = min_cz;
-  if (cz < 4) cz = 4;
+  // at least 4 planes per chunk, or 2 when 4 would leave CUs without a tile
+  // (small pyramid levels: the march of a chunk is their latency)
+  const int floor_cz = cols * ((nz + 3) / 4) < kMinTiles ? 2 : 4;
+  if (cz < floor_cz) cz = floor_cz;
   if (cz > nz) cz = nz;
   t.cz = cz;
   t.nchunks = (nz + cz - 1) / cz;

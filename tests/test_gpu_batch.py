@@ -54,6 +54,25 @@ def test_batch_matches_per_pair_runs(L, pairs):
         assert np.array_equal(host(v.field()), u_ref), i
 
 
+def test_batch_matches_staged_per_pair_run(L):
+    """A pair large enough for the per-pair LDS-staged update kernel: the
+    batched kernel's memory gathers give the same field bit for bit."""
+    from paper_2603_19371_amd import phantoms
+    sh = (67, 100, 330)
+    ph = phantoms.brain(sh, seed=7)
+    F, M = torch.from_numpy(ph.F).cuda(), torch.from_numpy(ph.M).cuda()
+    c = L.Context(sh, window=5)
+    c.begin(F, M)
+    c.step(F, M, 3)
+    ref, st_ref = host(c.field()), c.state()
+    b = L.Batch([sh], window=5)
+    b.begin([F], [M])
+    b.step(3, graph=False)
+    b.sync()
+    assert b.pair(0).state() == st_ref
+    assert np.array_equal(host(b.pair(0).field()), ref)
+
+
 def test_graph_replays_match_eager_steps(L, pairs):
     Fs, Ms = [F for F, _ in pairs], [M for _, M in pairs]
     eager = L.Batch(SHAPES, window=5)

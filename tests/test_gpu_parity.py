@@ -176,6 +176,28 @@ def test_gathers_at_volume_corners(L, orc, sign):
     assert e < 2e-6, e
 
 
+# Large enough for the LDS-staged form of the update (ragged in x, y and in
+# the last z-chunk).  With the smaller gradients most steps go beyond one
+# voxel, where the gather falls back to memory; with the larger none do.
+STAGED = (67, 100, 330)
+
+
+@pytest.mark.parametrize("scale, lam", [(1.0, 0.05), (0.1, 0.01)])
+def test_staged_update_matches_oracle(L, orc, scale, lam):
+    rng = np.random.default_rng(17)
+    u = rng.uniform(-2, 2, (3,) + STAGED).astype(np.float32)
+    g = (scale * rng.standard_normal((3,) + STAGED)).astype(np.float32)
+    ctx = L.Context(STAGED, step_eps=0.8)
+    out = host(ctx.update(dev(u), dev(g), 0.37, lam))
+    v = orc.closed_form(g, 0.37, lam)
+    far = (np.abs(0.8 * v) >= 1.0).any(axis=0).mean()
+    print(f"\n[staged update] {100 * far:.1f}% of the steps beyond one voxel")
+    ref = orc.integrate(u, v, 0.8, 1)
+    e = report("staged update", out, ref)
+    assert e < 2e-5, e
+    assert (far == 0.0) if scale == 1.0 else (0.3 < far < 0.9), far
+
+
 # ------------------------------------------------------------------ decision
 def test_decide_probe_matches_golden_tables(L):
     import json
