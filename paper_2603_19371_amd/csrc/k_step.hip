@@ -114,8 +114,12 @@ __global__ void __launch_bounds__(kSNT)
   __shared__ float s_u[kSlots][3][kSLY][kSLX];
   const int N = static_cast<int>(g.N), plane = g.nx * g.ny;
   const int lx = threadIdx.x % kSX, ly = threadIdx.x / kSX;
-  const int bx = blockIdx.x * kSX, by = blockIdx.y * kSY;
-  const int z0 = blockIdx.z * cz, z1 = min(z0 + cz, g.nz);
+  // one-dimensional grid; each XCD receives a contiguous range of tiles
+  // (x fastest, then y, then z-chunk) and shares their halos in its L2
+  const int tiles_x = (g.nx + kSX - 1) / kSX, tiles_y = (g.ny + kSY - 1) / kSY;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int bx = (tile % tiles_x) * kSX, by = ((tile / tiles_x) % tiles_y) * kSY;
+  const int z0 = (tile / (tiles_x * tiles_y)) * cz, z1 = min(z0 + cz, g.nz);
   const int x = bx + lx, y = by + ly;
   const bool own = x < g.nx && y < g.ny;
   const RBuf bu[3] = {make_rbuf_n(a.uin, N), make_rbuf_n(a.uin + N, N),
@@ -298,7 +302,7 @@ hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
     if ((long long)cols * (g.nz / 8) >= kStagedMinBlocks) {
       int cz = (int)(((long long)g.nz * cols + kStagedBlocks - 1) / kStagedBlocks);
       cz = std::max(cz, 8);
-      const dim3 sgrid((g.nx + kSX - 1) / kSX, (g.ny + kSY - 1) / kSY, (g.nz + cz - 1) / cz);
+      const dim3 sgrid(cols * ((g.nz + cz - 1) / cz));
       if (t == LMR_BF16)
         hipLaunchKernelGGL(k_update_staged<uint16_t>, sgrid, dim3(kSNT), 0, s,
                            static_cast<const uint16_t*>(M), g, st, G, U0, U1, u_in, u_out,
