@@ -57,8 +57,10 @@ lmr_status enqueue_attempt(lmr_ctx* c, const void* F, const void* M, int force) 
     return ev ? hipEventRecord(ev[2 * k + end], s) : hipSuccess;
   };
   LMR_HIP(mark(LMR_K_UPDATE, 0));
+  // the derivative of the candidate's warped image goes to graw, where P4
+  // reads it (voxel by voxel, before overwriting it with the raw gradient)
   LMR_HIP(launch_update(M, c->img, c->g, c->p, c->st, c->G, c->U[0], c->U[1], nullptr,
-                        nullptr, 0.0, 0.0, c->Mw, s));
+                        nullptr, 0.0, 0.0, c->Mw, c->graw, s));
   LMR_HIP(mark(LMR_K_UPDATE, 1));
   LMR_HIP(mark(LMR_K_FWD, 0));
   LMR_HIP(launch_fwd(F, c->img, c->Mw, c->g, c->p, c->st, c->maps, c->partials,
@@ -70,7 +72,7 @@ lmr_status enqueue_attempt(lmr_ctx* c, const void* F, const void* M, int force) 
   LMR_HIP(mark(LMR_K_DECIDE, 1));
   LMR_HIP(mark(LMR_K_BWD, 0));
   LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, c->st, c->U[0], c->U[1],
-                     nullptr, c->graw, s));
+                     nullptr, c->graw, c->graw, s));
   LMR_HIP(mark(LMR_K_BWD, 1));
   LMR_HIP(mark(LMR_K_SMOOTH, 0));
   LMR_HIP(launch_smooth(c->graw, c->g, c->p, c->st, c->G, s));
@@ -200,7 +202,7 @@ lmr_status lmr_begin(lmr_ctx* c, const void* F, const void* M, const float* fiel
   LMR_HIP(launch_decide(c->st, c->partials, c->nparts, c->g.N, c->dp, 1, -1, lambda0,
                         nullptr, s));
   LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, nullptr, nullptr,
-                     nullptr, c->U[0], c->graw, s));
+                     nullptr, c->U[0], nullptr, c->graw, s));
   LMR_HIP(launch_smooth(c->graw, c->g, c->p, nullptr, c->G, s));
   c->begun = true;
   return LMR_OK;
@@ -293,7 +295,7 @@ lmr_status lmr_loss_grad(lmr_ctx* c, const void* F, const void* M, const float* 
   if (g_raw || g_smooth) {
     float* gr = g_raw ? g_raw : c->graw;
     LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, nullptr, nullptr,
-                       nullptr, u, gr, s));
+                       nullptr, u, nullptr, gr, s));
     if (g_smooth) LMR_HIP(launch_smooth(gr, c->g, c->p, nullptr, g_smooth, s));
   }
   double L = 0.0;
@@ -307,7 +309,7 @@ lmr_status lmr_update(lmr_ctx* c, const float* u, const float* g_smooth, double 
                       double lambda, float* u_out) {
   if (!c || !u || !g_smooth || !u_out || u == u_out) return LMR_EINVAL;
   LMR_HIP(launch_update(nullptr, LMR_F32, c->g, c->p, nullptr, g_smooth, nullptr,
-                        nullptr, u, u_out, r, lambda, c->Mw, c->stream));
+                        nullptr, u, u_out, r, lambda, c->Mw, nullptr, c->stream));
   return LMR_OK;
 }
 

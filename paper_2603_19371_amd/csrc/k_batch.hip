@@ -154,6 +154,7 @@ __global__ void __launch_bounds__(kNT)
     pol.U0 = P.U0;
     pol.U1 = P.U1;
     pol.u_explicit = fresh(&P.st->cur) ? P.U1 : P.U0;  // the accepted candidate
+    pol.dMw = nullptr;
     pol.graw = P.graw;
     pol.g = P.g;
     pol.inv_n = P.inv_n;

@@ -67,8 +67,8 @@ hipError_t fwd_t(const T* F, const float* Mw, const Geom& g, const lmr_params& p
 template <typename T>
 hipError_t bwd_t(const T* F, const T* M, const float* Mw, const float* maps,
                  const Geom& g, const lmr_params& p, const DevState* st,
-                 const float* U0, const float* U1, const float* ue, float* graw,
-                 hipStream_t s) {
+                 const float* U0, const float* U1, const float* ue, const float* dMw,
+                 float* graw, hipStream_t s) {
   BwdPol<T> pol;
   pol.F = F;
   pol.M = M;
@@ -77,6 +77,7 @@ hipError_t bwd_t(const T* F, const T* M, const float* Mw, const float* maps,
   pol.U0 = U0;
   pol.U1 = U1;
   pol.u_explicit = ue;
+  pol.dMw = dMw;
   pol.graw = graw;
   pol.g = g;
   pol.inv_n = 1.0 / ((double)p.window * p.window * p.window);
@@ -115,12 +116,12 @@ hipError_t launch_fwd(const void* F, lmr_dtype t, const float* Mw, const Geom& g
 hipError_t launch_bwd(const void* F, const void* M, lmr_dtype t, const float* Mw,
                       const float* maps, const Geom& g, const lmr_params& p,
                       const DevState* st, const float* U0, const float* U1,
-                      const float* ue, float* graw, hipStream_t s) {
+                      const float* ue, const float* dMw, float* graw, hipStream_t s) {
   if (t == LMR_BF16)
     return bwd_t(static_cast<const uint16_t*>(F), static_cast<const uint16_t*>(M), Mw,
-                 maps, g, p, st, U0, U1, ue, graw, s);
+                 maps, g, p, st, U0, U1, ue, dMw, graw, s);
   return bwd_t(static_cast<const float*>(F), static_cast<const float*>(M), Mw, maps, g,
-               p, st, U0, U1, ue, graw, s);
+               p, st, U0, U1, ue, dMw, graw, s);
 }
 
 hipError_t launch_smooth(const float* graw, const Geom& g, const lmr_params& p,

@@ -55,16 +55,18 @@ __global__ void __launch_bounds__(kBX* kBY)
     k_update(const T* __restrict__ M, Geom g, const DevState* __restrict__ st,
              const float* __restrict__ G, float* U0, float* U1,
              const float* u_in, float* u_out, float r_arg, float lam_arg,
-             float eps, int compositive, float* __restrict__ Mw) {
+             float eps, int compositive, float* __restrict__ Mw, float* dMw) {
   UpdateArgs a;
   if (st) {
     if (st->stalled) return;
     a = update_args_from_state(st, U0, U1, G, Mw, eps, compositive);
+    a.dMw = dMw;
   } else {
     a.uin = u_in;
     a.uo = u_out;
     a.G = G;
     a.Mw = Mw;
+    a.dMw = nullptr;
     a.r = r_arg;
     a.lam = lam_arg;
     a.eps = eps;
@@ -96,16 +98,18 @@ __global__ void __launch_bounds__(kSNT)
     k_update_staged(const T* __restrict__ M, Geom g, const DevState* __restrict__ st,
                     const float* __restrict__ G, float* U0, float* U1, const float* u_in,
                     float* u_out, float r_arg, float lam_arg, float eps,
-                    float* __restrict__ Mw, int cz) {
+                    float* __restrict__ Mw, float* dMw, int cz) {
   UpdateArgs a;
   if (st) {
     if (st->stalled) return;
     a = update_args_from_state(st, U0, U1, G, Mw, eps, 1);
+    a.dMw = dMw;
   } else {
     a.uin = u_in;
     a.uo = u_out;
     a.G = G;
     a.Mw = Mw;
+    a.dMw = nullptr;
     a.r = r_arg;
     a.lam = lam_arg;
     a.eps = eps;
@@ -228,9 +232,14 @@ __global__ void __launch_bounds__(kSNT)
     a.uo[2 * N + i] = n2;
     if (M && a.Mw) {
       const BCell cm = make_bcell(g, x, y, z, n0, n1, n2);
-      float v[8];
+      float v[8], d[3];
       bcorners<T>(bm, g, cm, v);
-      a.Mw[i] = binterp(cm, v, nullptr);
+      a.Mw[i] = binterp(cm, v, a.dMw ? d : nullptr);
+      if (a.dMw) {
+        a.dMw[i] = d[0];
+        a.dMw[N + i] = d[1];
+        a.dMw[2 * N + i] = d[2];
+      }
     }
   }
 }
@@ -291,7 +300,7 @@ hipError_t launch_warp(const void* M, lmr_dtype t, const float* u, const Geom& g
 hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
                          const lmr_params& p, const DevState* st, const float* G,
                          float* U0, float* U1, const float* u_in, float* u_out,
-                         double r, double lambda, float* Mw, hipStream_t s) {
+                         double r, double lambda, float* Mw, float* dMw, hipStream_t s) {
   dim3 blk(kBX, kBY);
   const float rf = static_cast<float>(r), lf = static_cast<float>(lambda);
   const float eps = static_cast<float>(p.step_eps);
@@ -306,11 +315,11 @@ hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
       if (t == LMR_BF16)
         hipLaunchKernelGGL(k_update_staged<uint16_t>, sgrid, dim3(kSNT), 0, s,
                            static_cast<const uint16_t*>(M), g, st, G, U0, U1, u_in, u_out,
-                           rf, lf, eps, Mw, cz);
+                           rf, lf, eps, Mw, dMw, cz);
       else
         hipLaunchKernelGGL(k_update_staged<float>, sgrid, dim3(kSNT), 0, s,
                            static_cast<const float*>(M), g, st, G, U0, U1, u_in, u_out, rf,
-                           lf, eps, Mw, cz);
+                           lf, eps, Mw, dMw, cz);
       return hipGetLastError();
     }
   }
@@ -318,11 +327,11 @@ hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
   if (t == LMR_BF16)
     hipLaunchKernelGGL(k_update<uint16_t>, grid, blk, 0, s,
                        static_cast<const uint16_t*>(M), g, st, G, U0, U1, u_in, u_out,
-                       rf, lf, eps, p.compositive, Mw);
+                       rf, lf, eps, p.compositive, Mw, dMw);
   else
     hipLaunchKernelGGL(k_update<float>, grid, blk, 0, s,
                        static_cast<const float*>(M), g, st, G, U0, U1, u_in, u_out, rf,
-                       lf, eps, p.compositive, Mw);
+                       lf, eps, p.compositive, Mw, dMw);
   return hipGetLastError();
 }
 

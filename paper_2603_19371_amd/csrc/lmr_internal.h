@@ -328,10 +328,12 @@ hipError_t launch_warp(const void* M, lmr_dtype t, const float* u, const Geom& g
                        float* Mw, float* dMw, hipStream_t s);
 // P1: closed form + compositive integration + warp of M at the candidate.
 // Explicit mode (st == null): reads u_in, g_smooth, r, lambda, writes u_out.
+// In state mode dMw (may be null) receives the derivative of the warped image
+// at the candidate, for P4.
 hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
                          const lmr_params& p, const DevState* st,
                          const float* G, float* U0, float* U1, const float* u_in,
-                         float* u_out, double r, double lambda, float* Mw,
+                         float* u_out, double r, double lambda, float* Mw, float* dMw,
                          hipStream_t s);
 // P2: LNCC forward; writes adjoint maps, per-block partials and optionally cc.
 hipError_t launch_fwd(const void* F, lmr_dtype t, const float* Mw, const Geom& g,
@@ -343,11 +345,14 @@ hipError_t launch_decide(DevState* st, const double* partials, int nparts,
                          long long N, const DecideParams& dp, int mode, int force,
                          double lambda0, double* probe, hipStream_t s);
 // P4: LNCC backward and warp backward -> raw gradient.  The field is U[cur]
-// in state mode, u_explicit otherwise.
+// in state mode, u_explicit otherwise.  dMw (may be null, may alias graw):
+// the derivative of M at x + u(x) stored by P1 for the accepted candidate;
+// null gathers it from M.
 hipError_t launch_bwd(const void* F, const void* M, lmr_dtype t, const float* Mw,
                       const float* maps, const Geom& g, const lmr_params& p,
                       const DevState* st, const float* U0, const float* U1,
-                      const float* u_explicit, float* graw, hipStream_t s);
+                      const float* u_explicit, const float* dMw, float* graw,
+                      hipStream_t s);
 // P5: Gaussian smoothing of the raw gradient.
 hipError_t launch_smooth(const float* graw, const Geom& g, const lmr_params& p,
                          const DevState* st, float* out, hipStream_t s);

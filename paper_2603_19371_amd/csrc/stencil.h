@@ -268,7 +268,11 @@ struct BwdPol {
   const float* U0;  // field ping-pong (state mode: the field is U[cur])
   const float* U1;
   const float* u_explicit;  // the field when no state is given
-  float* __restrict__ graw;
+  // derivative of M at x + u(x) as the update kernel stored it for the
+  // candidate (null: gathered here); may alias graw (read, then overwritten,
+  // by the thread of the same voxel)
+  const float* dMw;
+  float* graw;
   Geom g;
   double inv_n;
   struct Local {
@@ -302,10 +306,17 @@ struct BwdPol {
     const double fj = ldf(F, i), mj = Mw[i];
     const double dS = (fj * B[0] - B[1] + 2.0 * mj * B[2] - 2.0 * B[3]) * inv_n;
     const float d = static_cast<float>(dS);
-    float gm[3], v[8];
-    const BCell c = make_bcell(g, x, y, z, u[i], u[N + i], u[2 * N + i]);
-    bcorners<T>(loc.bM, g, c, v);
-    binterp(c, v, gm);
+    float gm[3];
+    if (dMw) {
+      gm[0] = dMw[i];
+      gm[1] = dMw[N + i];
+      gm[2] = dMw[2 * N + i];
+    } else {
+      float v[8];
+      const BCell c = make_bcell(g, x, y, z, u[i], u[N + i], u[2 * N + i]);
+      bcorners<T>(loc.bM, g, c, v);
+      binterp(c, v, gm);
+    }
     graw[i] = -d * gm[0];
     graw[N + i] = -d * gm[1];
     graw[2 * N + i] = -d * gm[2];

@@ -14,6 +14,7 @@ struct UpdateArgs {
   float* uo;         // candidate field [3][N]
   const float* G;    // smoothed gradient of the accepted field [3][N]
   float* Mw;         // warped moving image at the candidate (null: skip)
+  float* dMw;        // its spatial derivative [3][N] (null: skip), for P4
   float r, lam, eps;
   int compositive;
 };
@@ -47,9 +48,14 @@ __device__ __forceinline__ void update_voxel(const T* __restrict__ M, const Geom
   a.uo[2 * N + i] = n2;
   if (M && a.Mw) {
     const BCell c = make_bcell(g, x, y, z, n0, n1, n2);
-    float v[8];
+    float v[8], d[3];
     bcorners<T>(make_rbuf_n(M, N), g, c, v);
-    a.Mw[i] = binterp(c, v, nullptr);
+    a.Mw[i] = binterp(c, v, a.dMw ? d : nullptr);
+    if (a.dMw) {
+      a.dMw[i] = d[0];
+      a.dMw[N + i] = d[1];
+      a.dMw[2 * N + i] = d[2];
+    }
   }
 }
 
@@ -65,7 +71,7 @@ __device__ __forceinline__ void update_voxels(const T* __restrict__ M, const Geo
   const int N = static_cast<int>(g.N);
   int idx[V];
   bool ok[V];
-  float e[V][3], n[V][3], mw[V];
+  float e[V][3], n[V][3], mw[V], dm[V][3];
 #pragma unroll
   for (int j = 0; j < V; ++j) {
     ok[j] = z0 + j < g.nz;
@@ -109,7 +115,7 @@ __device__ __forceinline__ void update_voxels(const T* __restrict__ M, const Geo
       bcorners<T>(bm, g, c[j], v[j]);
     }
 #pragma unroll
-    for (int j = 0; j < V; ++j) mw[j] = binterp(c[j], v[j], nullptr);
+    for (int j = 0; j < V; ++j) mw[j] = binterp(c[j], v[j], a.dMw ? dm[j] : nullptr);
   }
 #pragma unroll
   for (int j = 0; j < V; ++j) {
@@ -118,7 +124,14 @@ __device__ __forceinline__ void update_voxels(const T* __restrict__ M, const Geo
     a.uo[i] = n[j][0];
     a.uo[N + i] = n[j][1];
     a.uo[2 * N + i] = n[j][2];
-    if (M && a.Mw) a.Mw[i] = mw[j];
+    if (M && a.Mw) {
+      a.Mw[i] = mw[j];
+      if (a.dMw) {
+        a.dMw[i] = dm[j][0];
+        a.dMw[N + i] = dm[j][1];
+        a.dMw[2 * N + i] = dm[j][2];
+      }
+    }
   }
 }
 
@@ -135,6 +148,7 @@ __device__ __forceinline__ UpdateArgs update_args_from_state(const DevState* st,
   a.uo = cur ? U0 : U1;
   a.G = G;
   a.Mw = Mw;
+  a.dMw = nullptr;
   a.r = static_cast<float>(st->r);
   a.lam = static_cast<float>(st->lambda);
   a.eps = eps;
