@@ -50,15 +50,16 @@ HBM_PEAK_GBS = 8000.0
 # outputs (each array read or written once; s = bytes per image voxel).
 def kernel_bytes(s):
     return {
-        "update": 12 + 12 + s + 12 + 4,      # g, u, M gather, u~, warped M
+        # g, u, M gather -> u~, warped M and its derivative (read by lncc_bwd)
+        "update": 12 + 12 + s + 12 + 4 + 12,
         "lncc_fwd": s + 4 + 16,              # F, warped M -> 4 adjoint maps
         "decide": 0,
-        "lncc_bwd": 16 + s + 4 + 12 + s + 12,  # maps, F, Mw, u, M gather -> g
+        "lncc_bwd": 16 + s + 4 + 12 + 12,    # maps, F, Mw, dMw -> g
         "smooth": 12 + 12,
     }
 
 
-# Whole attempt (SURVEY-level algorithmic figure): read F, M, u, write u~,
+# Whole attempt (what the method itself must move): read F, M, u, write u~,
 # persist the smoothed gradient between attempts (write + read).
 def attempt_bytes(s):
     return 2 * s + 12 + 12 + 24

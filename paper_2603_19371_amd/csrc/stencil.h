@@ -49,9 +49,13 @@ __host__ __device__ inline Tiling make_tiling(int nz, int ny, int nx, int ty,
   const int want = (target_tiles + cols - 1) / cols;
   int cz = (nz + want - 1) / want;
   if (cols * ((nz + min_cz - 1) / min_cz) >= target_tiles / 2 && cz < min_cz) cz = min_cz;
-  // at least 4 planes per chunk, or 2 when 4 would leave CUs without a tile
-  // (small pyramid levels: the march of a chunk is their latency)
-  const int floor_cz = cols * ((nz + 3) / 4) < kMinTiles ? 2 : 4;
+  // floor on the chunk length: 8 planes while that still gives every CU a
+  // tile (the 2R halo planes stay a moderate share), else 4, else 2 when 4
+  // would leave CUs without a tile (small pyramid levels: the march of a
+  // chunk is their latency)
+  const int floor_cz = cols * ((nz + 7) / 8) >= kMinTiles   ? 8
+                       : cols * ((nz + 3) / 4) >= kMinTiles ? 4
+                                                            : 2;
   if (cz < floor_cz) cz = floor_cz;
   if (cz > nz) cz = nz;
   t.cz = cz;
