@@ -179,6 +179,22 @@ __global__ void __launch_bounds__(kSNT)
 #pragma unroll
   for (int c = 0; c < 3; ++c)
     gn[c] = bld<float>(bg[c], own ? static_cast<unsigned>(z0 * plane) + col : kFarIndex);
+  // The image gather M(x + u~) of a plane stays in flight while the next
+  // plane's field work runs; it is finished (interpolated and stored) then.
+  const bool warp = M && a.Mw;
+  BCell pc;
+  float pv[8];
+  int pi = -1;  // voxel of the pending image gather (-1: none)
+  auto finish = [&]() {
+    if (pi < 0) return;
+    float d[3];
+    a.Mw[pi] = binterp(pc, pv, a.dMw ? d : nullptr);
+    if (a.dMw) {
+      a.dMw[pi] = d[0];
+      a.dMw[N + pi] = d[1];
+      a.dMw[2 * N + pi] = d[2];
+    }
+  };
   for (int z = z0; z < z1; ++z) {
     // slot(z+1) last held plane z-3, whose readers finished before the
     // barrier of the previous iteration
@@ -230,18 +246,14 @@ __global__ void __launch_bounds__(kSNT)
     a.uo[i] = n0;
     a.uo[N + i] = n1;
     a.uo[2 * N + i] = n2;
-    if (M && a.Mw) {
-      const BCell cm = make_bcell(g, x, y, z, n0, n1, n2);
-      float v[8], d[3];
-      bcorners<T>(bm, g, cm, v);
-      a.Mw[i] = binterp(cm, v, a.dMw ? d : nullptr);
-      if (a.dMw) {
-        a.dMw[i] = d[0];
-        a.dMw[N + i] = d[1];
-        a.dMw[2 * N + i] = d[2];
-      }
+    finish();
+    if (warp) {
+      pc = make_bcell(g, x, y, z, n0, n1, n2);
+      bcorners<T>(bm, g, pc, pv);
+      pi = i;
     }
   }
+  if (own) finish();
 }
 
 constexpr int kDecideThreads = 256;
