@@ -34,7 +34,7 @@ struct lmr_batch {
   int cus = 0, max_blocks_per_cu = 0;
   // tuned configuration
   int target_tiles = 2048, min_cz = 16, blocks_per_cu = 0;
-  int n_vox_items = 0, n_tiles = 0;
+  int n_update_items = 0, n_tiles = 0;
   unsigned long long timeout = 0;  // barrier timeout in wall-clock ticks
   std::map<int, hipGraphExec_t> graphs;  // n_iters -> instantiated graph
   bool begun = false;
@@ -52,16 +52,18 @@ void drop_graphs(lmr_batch* b) {
 // Rebuild the work lists for the current tiling knobs and upload the table.
 lmr_status layout(lmr_batch* b) {
   int vox = 0, tiles = 0;
-  const int ty = batch_tile_rows(), nt = batch_block_threads();
+  const int ty = batch_tile_rows();
   for (int i = 0; i < b->npairs; ++i) {
     BatchPair& P = b->host[i];
     P.t = make_tiling(P.g.nz, P.g.ny, P.g.nx, ty, b->target_tiles, b->min_cz);
-    P.vox0 = vox;
+    P.utile0 = vox;
     P.tile0 = tiles;
-    vox += static_cast<int>((P.g.N + nt - 1) / nt);
+    vox += ((P.g.nx + kBatchUpdateTX - 1) / kBatchUpdateTX) *
+           ((P.g.ny + kBatchUpdateTY - 1) / kBatchUpdateTY) *
+           ((P.g.nz + kBatchUpdateCz - 1) / kBatchUpdateCz);
     tiles += P.t.tiles();
   }
-  b->n_vox_items = vox;
+  b->n_update_items = vox;
   b->n_tiles = tiles;
   LMR_HIP(hipMemcpyAsync(b->dev_pairs, b->host.data(), sizeof(BatchPair) * b->npairs,
                          hipMemcpyHostToDevice, b->stream));
@@ -81,7 +83,7 @@ int grid_of(const lmr_batch* b) {
 lmr_status enqueue_steps(lmr_batch* b, int n) {
   const int grid = grid_of(b);
   for (int i = 0; i < n; ++i)
-    LMR_HIP(launch_batch_attempt(b->kernel, grid, b->dev_pairs, b->npairs, b->n_vox_items,
+    LMR_HIP(launch_batch_attempt(b->kernel, grid, b->dev_pairs, b->npairs, b->n_update_items,
                                  b->n_tiles, b->ctl, b->dp, b->timeout, b->stream));
   return LMR_OK;
 }

@@ -25,6 +25,8 @@ namespace {
 
 constexpr int kTY = 8;
 constexpr int kNT = kTX * kTY;
+static_assert(kBatchUpdateTX == kSX && kBatchUpdateTY == kSY && kNT == kSNT,
+              "update work items are staged-update tiles of one block");
 
 // Grid-wide barrier among `nblocks` co-resident blocks (two-level arrival on
 // monotonic counters, see BatchCtl).  A wait longer than `timeout` ticks of
@@ -87,29 +89,46 @@ __device__ __forceinline__ int owner(const BatchPair* __restrict__ pairs, int np
                                      int it, bool tiles) {
   int p = 0;
   for (int k = 1; k < npairs; ++k)
-    if ((tiles ? pairs[k].tile0 : pairs[k].vox0) <= it) p = k;
+    if ((tiles ? pairs[k].tile0 : pairs[k].utile0) <= it) p = k;
   return p;
 }
 
 template <int RB, int RG, typename T>
 __global__ void __launch_bounds__(kNT)
-    k_batch_attempt(const BatchPair* __restrict__ pairs, int npairs, int n_vox_items,
+    k_batch_attempt(const BatchPair* __restrict__ pairs, int npairs, int n_update_items,
                     int n_tiles, BatchCtl* ctl, DecideParams dp,
                     unsigned long long timeout) {
   const int nb = gridDim.x;
+  // the phases are separated by grid barriers, so their LDS is overlaid
+  __shared__ union {
+    StagedLds upd;
+    StencilLds<RB, kTY, FwdPol<T, kNT>> fwd;
+    StencilLds<RB, kTY, BwdPol<T>> bwd;
+    StencilLds<RG, kTY, SmoothPol<RG>> smo;
+  } lds;
   // after a barrier timeout every later launch returns at once
   if (__hip_atomic_load(&ctl->error.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
 
-  // P1: closed form, compositive integration, candidate warp
-  for (int it = blockIdx.x; it < n_vox_items; it += nb) {
+  // P1: closed form, compositive integration, candidate warp (and its
+  // derivative, which P4 reads), one staged tile per work item
+  for (int it = blockIdx.x; it < n_update_items; it += nb) {
     const BatchPair& P = pairs[owner(pairs, npairs, it, false)];
     if (P.st->stalled) continue;
-    const int v = (it - P.vox0) * kNT + threadIdx.x;
-    if (v >= static_cast<int>(P.g.N)) continue;
-    const int x = v % P.g.nx, y = (v / P.g.nx) % P.g.ny, z = v / (P.g.nx * P.g.ny);
-    const UpdateArgs a =
-        update_args_from_state(P.st, P.U0, P.U1, P.G, P.Mw, P.eps, P.compositive);
-    update_voxel(static_cast<const T*>(P.M), P.g, a, x, y, z);
+    UpdateArgs a = update_args_from_state(P.st, P.U0, P.U1, P.G, P.Mw, P.eps, P.compositive);
+    a.dMw = P.graw;
+    const int local = it - P.utile0;
+    const int tx = (P.g.nx + kSX - 1) / kSX, ty = (P.g.ny + kSY - 1) / kSY;
+    const int bx = (local % tx) * kSX, by = ((local / tx) % ty) * kSY;
+    const int z0 = (local / (tx * ty)) * kBatchUpdateCz;
+    const int z1 = min(z0 + kBatchUpdateCz, P.g.nz);
+    if (P.compositive) {
+      staged_update_tile(static_cast<const T*>(P.M), P.g, a, bx, by, z0, z1, lds.upd);
+    } else {
+      const int x = bx + static_cast<int>(threadIdx.x) % kSX;
+      const int y = by + static_cast<int>(threadIdx.x) / kSX;
+      if (x < P.g.nx && y < P.g.ny)
+        for (int z = z0; z < z1; ++z) update_voxel(static_cast<const T*>(P.M), P.g, a, x, y, z);
+    }
   }
   if (!grid_sync(ctl, nb, timeout)) return;
 
@@ -130,7 +149,7 @@ __global__ void __launch_bounds__(kNT)
     int x0, y0, z0;
     tile_origin(P.t, local, kTY, x0, y0, z0);
     auto loc = pol.begin_block(P.st);
-    stencil_tile<RB, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc);
+    stencil_tile<RB, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc, lds.fwd);
     pol.end_tile(loc, local);
   }
   if (!grid_sync(ctl, nb, timeout)) return;
@@ -154,14 +173,14 @@ __global__ void __launch_bounds__(kNT)
     pol.U0 = P.U0;
     pol.U1 = P.U1;
     pol.u_explicit = fresh(&P.st->cur) ? P.U1 : P.U0;  // the accepted candidate
-    pol.dMw = nullptr;
+    pol.dMw = P.graw;  // stored there by P1 for the candidate
     pol.graw = P.graw;
     pol.g = P.g;
     pol.inv_n = P.inv_n;
     int x0, y0, z0;
     tile_origin(P.t, it - P.tile0, kTY, x0, y0, z0);
     auto loc = pol.begin_block(nullptr);
-    stencil_tile<RB, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc);
+    stencil_tile<RB, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc, lds.bwd);
   }
   if (!grid_sync(ctl, nb, timeout)) return;
 
@@ -178,7 +197,7 @@ __global__ void __launch_bounds__(kNT)
     int x0, y0, z0;
     tile_origin(P.t, it - P.tile0, kTY, x0, y0, z0);
     auto loc = pol.begin_block(P.st);
-    stencil_tile<RG, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc);
+    stencil_tile<RG, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc, lds.smo);
   }
 }
 
@@ -219,10 +238,10 @@ const void* batch_kernel(lmr_dtype t, int box_radius, int gauss_radius) {
 }
 
 hipError_t launch_batch_attempt(const void* kernel, int grid, const BatchPair* pairs,
-                                int npairs, int n_vox_items, int n_tiles, BatchCtl* ctl,
+                                int npairs, int n_update_items, int n_tiles, BatchCtl* ctl,
                                 const DecideParams& dp, unsigned long long timeout,
                                 hipStream_t s) {
-  void* args[] = {&pairs, &npairs, &n_vox_items, &n_tiles, &ctl,
+  void* args[] = {&pairs, &npairs, &n_update_items, &n_tiles, &ctl,
                   const_cast<DecideParams*>(&dp), &timeout};
   return hipLaunchKernel(kernel, dim3(grid), dim3(kNT), args, 0, s);
 }

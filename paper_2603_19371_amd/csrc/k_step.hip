@@ -78,19 +78,8 @@ __global__ void __launch_bounds__(kBX* kBY)
   update_voxels<T, kUpdZ>(M, g, a, x, y, blockIdx.z * kUpdZ);
 }
 
-// The same attempt step with the accepted field staged in LDS.  A block owns
-// a 32 x 8 column of voxels and marches along z through a chunk of planes,
-// keeping the planes z-1, z, z+1 of the three field channels (with a
-// one-voxel halo in x and y) in a ring of LDS slots.  The compositive
-// gather u(x + eps du) reads its eight corners from LDS whenever every
-// component of eps du lies in [-1, 1) (the cell's corners are then within one
-// voxel of x), and from memory otherwise.  The staged values are the field's
-// own, and out-of-volume corners carry weight 0 either way, so each voxel's
-// result is that of update_voxel (up to the sign of an exact zero).
-constexpr int kSX = 32, kSY = 8, kSNT = kSX * kSY;
-constexpr int kSLX = kSX + 2, kSLY = kSY + 2, kSPOS = kSLX * kSLY;
-constexpr int kSPER = (kSPOS + kSNT - 1) / kSNT;
-constexpr int kSlots = 4;  // planes z-1..z+1 in use while z+2 is written
+// The update with the accepted field staged in LDS (staged_update_tile),
+// one tile per block.
 constexpr int kStagedMinBlocks = 1024, kStagedBlocks = 1024;
 
 template <typename T>
@@ -115,145 +104,13 @@ __global__ void __launch_bounds__(kSNT)
     a.eps = eps;
     a.compositive = 1;
   }
-  __shared__ float s_u[kSlots][3][kSLY][kSLX];
-  const int N = static_cast<int>(g.N), plane = g.nx * g.ny;
-  const int lx = threadIdx.x % kSX, ly = threadIdx.x / kSX;
   // one-dimensional grid; each XCD receives a contiguous range of tiles
   // (x fastest, then y, then z-chunk) and shares their halos in its L2
   const int tiles_x = (g.nx + kSX - 1) / kSX, tiles_y = (g.ny + kSY - 1) / kSY;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int bx = (tile % tiles_x) * kSX, by = ((tile / tiles_x) % tiles_y) * kSY;
   const int z0 = (tile / (tiles_x * tiles_y)) * cz, z1 = min(z0 + cz, g.nz);
-  const int x = bx + lx, y = by + ly;
-  const bool own = x < g.nx && y < g.ny;
-  const RBuf bu[3] = {make_rbuf_n(a.uin, N), make_rbuf_n(a.uin + N, N),
-                      make_rbuf_n(a.uin + 2 * N, N)};
-
-  // staged positions of this thread (padding positions read 0)
-  int pidx[kSPER];
-  bool pin[kSPER];
-#pragma unroll
-  for (int p = 0; p < kSPER; ++p) {
-    const int i = threadIdx.x + p * kSNT;
-    const int yy = i / kSLX, xx = i - yy * kSLX;
-    const int gy = by - 1 + yy, gx = bx - 1 + xx;
-    pin[p] = i < kSPOS && (unsigned)gy < (unsigned)g.ny && (unsigned)gx < (unsigned)g.nx;
-    pidx[p] = pin[p] ? gy * g.nx + gx : 0;
-  }
-  float pre[kSPER][3];
-  auto fetch = [&](int zi) {
-    const bool zin = (unsigned)zi < (unsigned)g.nz;
-#pragma unroll
-    for (int p = 0; p < kSPER; ++p) {
-      const unsigned o = (zin && pin[p]) ? static_cast<unsigned>(zi * plane + pidx[p])
-                                         : kFarIndex;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) pre[p][c] = bld<float>(bu[c], o);
-    }
-  };
-  auto slot = [](int zi) { return (zi + kSlots) % kSlots; };  // zi >= -1
-  auto commit = [&](int zi) {
-    const int sl = slot(zi);
-#pragma unroll
-    for (int p = 0; p < kSPER; ++p) {
-      const int i = threadIdx.x + p * kSNT;
-      if (i < kSPOS) {
-        const int yy = i / kSLX, xx = i - yy * kSLX;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) s_u[sl][c][yy][xx] = pre[p][c];
-      }
-    }
-  };
-
-  fetch(z0 - 1);
-  commit(z0 - 1);
-  fetch(z0);
-  commit(z0);
-  fetch(z0 + 1);
-  const RBuf bm = make_rbuf_n(M, N);
-  const RBuf bg[3] = {make_rbuf_n(a.G, N), make_rbuf_n(a.G + N, N),
-                      make_rbuf_n(a.G + 2 * N, N)};
-  // the gradient of the next plane is in flight while a plane is processed
-  const unsigned col = own ? static_cast<unsigned>(y * g.nx + x) : kFarIndex;
-  float gn[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-    gn[c] = bld<float>(bg[c], own ? static_cast<unsigned>(z0 * plane) + col : kFarIndex);
-  // The image gather M(x + u~) of a plane stays in flight while the next
-  // plane's field work runs; it is finished (interpolated and stored) then.
-  const bool warp = M && a.Mw;
-  BCell pc;
-  float pv[8];
-  int pi = -1;  // voxel of the pending image gather (-1: none)
-  auto finish = [&]() {
-    if (pi < 0) return;
-    float d[3];
-    a.Mw[pi] = binterp(pc, pv, a.dMw ? d : nullptr);
-    if (a.dMw) {
-      a.dMw[pi] = d[0];
-      a.dMw[N + pi] = d[1];
-      a.dMw[2 * N + pi] = d[2];
-    }
-  };
-  for (int z = z0; z < z1; ++z) {
-    // slot(z+1) last held plane z-3, whose readers finished before the
-    // barrier of the previous iteration
-    commit(z + 1);
-    if (z + 2 <= z1) fetch(z + 2);
-    const float g0 = gn[0], g1 = gn[1], g2 = gn[2];
-    if (z + 1 < z1) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        gn[c] = bld<float>(bg[c], own ? static_cast<unsigned>((z + 1) * plane) + col
-                                      : kFarIndex);
-    }
-    __syncthreads();
-    if (!own) continue;
-    const int i = (z * g.ny + y) * g.nx + x;
-    const float s = -a.r / fmaf(g2, g2, fmaf(g1, g1, fmaf(g0, g0, a.lam)));
-    const float e0 = a.eps * (s * g0), e1 = a.eps * (s * g1), e2 = a.eps * (s * g2);
-    const BCell c = make_bcell(g, x, y, z, e0, e1, e2);
-    float b[3];
-    if (e0 >= -1.0f && e0 < 1.0f && e1 >= -1.0f && e1 < 1.0f && e2 >= -1.0f && e2 < 1.0f) {
-      // lower corner (x + floor(e0), y + floor(e1), z + floor(e2)), each
-      // floor in {-1, 0}: staged column lx + floor + 1, row ly + floor + 1
-      const int cx = lx + 1 + (e0 < 0.0f ? -1 : 0);
-      const int cy = ly + 1 + (e1 < 0.0f ? -1 : 0);
-      const int cz0 = z + (e2 < 0.0f ? -1 : 0);
-      const int s0 = slot(cz0), s1 = slot(cz0 + 1);
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        float v[8];
-        v[0] = s_u[s0][ch][cy][cx];
-        v[1] = s_u[s0][ch][cy][cx + 1];
-        v[2] = s_u[s0][ch][cy + 1][cx];
-        v[3] = s_u[s0][ch][cy + 1][cx + 1];
-        v[4] = s_u[s1][ch][cy][cx];
-        v[5] = s_u[s1][ch][cy][cx + 1];
-        v[6] = s_u[s1][ch][cy + 1][cx];
-        v[7] = s_u[s1][ch][cy + 1][cx + 1];
-        b[ch] = binterp(c, v, nullptr);
-      }
-    } else {
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        float v[8];
-        bcorners<float>(bu[ch], g, c, v);
-        b[ch] = binterp(c, v, nullptr);
-      }
-    }
-    const float n0 = e0 + b[0], n1 = e1 + b[1], n2 = e2 + b[2];
-    a.uo[i] = n0;
-    a.uo[N + i] = n1;
-    a.uo[2 * N + i] = n2;
-    finish();
-    if (warp) {
-      pc = make_bcell(g, x, y, z, n0, n1, n2);
-      bcorners<T>(bm, g, pc, pv);
-      pi = i;
-    }
-  }
-  if (own) finish();
+  staged_update_tile(M, g, a, bx, by, z0, z1);
 }
 
 constexpr int kDecideThreads = 256;

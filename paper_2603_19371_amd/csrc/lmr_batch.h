@@ -20,7 +20,7 @@ struct BatchPair {
   double* partials;  // one slot per stencil tile of this pair
   DevState* st;
   Tiling t;          // stencil tiling of this pair
-  int vox0;          // first update work item of this pair
+  int utile0;        // first update work item (32 x 8 x kBatchUpdateCz tile) of this pair
   int tile0;         // first stencil work item of this pair
   float eps;
   int compositive;
@@ -39,6 +39,8 @@ struct BatchPair {
 // it is at, and no plain store to a counter has to be ordered against the
 // atomics of blocks on other chiplets.
 constexpr int kBarGroups = 8;
+// update work item: a 32 x 8 column (the staged update's tile) over 16 planes
+constexpr int kBatchUpdateTX = 32, kBatchUpdateTY = 8, kBatchUpdateCz = 16;
 struct BatchCtl {
   struct alignas(128) Line {
     unsigned long long v;
@@ -55,7 +57,7 @@ int batch_block_threads();
 // 0..4), or null when that combination is not instantiated.
 const void* batch_kernel(lmr_dtype t, int box_radius, int gauss_radius);
 hipError_t launch_batch_attempt(const void* kernel, int grid, const BatchPair* pairs,
-                                int npairs, int n_vox_items, int n_tiles, BatchCtl* ctl,
+                                int npairs, int n_update_items, int n_tiles, BatchCtl* ctl,
                                 const DecideParams& dp, unsigned long long timeout,
                                 hipStream_t s);
 

@@ -63,16 +63,25 @@ __host__ __device__ inline Tiling make_tiling(int nz, int ny, int nx, int ty,
   return t;
 }
 
-// Runs the stencil over tile (x0, y0, z0..z1) with the whole block.
+// LDS of one stencil tile: the staged raw inputs and the y-pass sums.
+template <int R, int TY, class P>
+struct StencilLds {
+  float in[P::NRAW][TY + 2 * R][kTX + 2 * R];
+  typename P::Acc y[P::NCH][TY][kTX + 2 * R];
+};
+
+// Runs the stencil over tile (x0, y0, z0..z1) with the whole block, in the
+// LDS `sm` (a kernel that runs several phases can overlay their LDS).
 template <int R, int TY, class P>
 __device__ __forceinline__ void stencil_tile(const P& pol, const Geom& g, int x0, int y0,
-                                             int z0, int z1, typename P::Local& loc) {
+                                             int z0, int z1, typename P::Local& loc,
+                                             StencilLds<R, TY, P>& sm) {
   using A = typename P::Acc;
   constexpr int NR = P::NRAW, NC = P::NCH;
   constexpr int W = 2 * R + 1, LX = kTX + 2 * R, LY = TY + 2 * R, NT = kTX * TY;
   constexpr int NPOS = LX * LY, PER = (NPOS + NT - 1) / NT;
-  __shared__ float s_in[NR][LY][LX];
-  __shared__ A s_y[NC][TY][LX];
+  auto& s_in = sm.in;
+  auto& s_y = sm.y;
 
   const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
   const int gx = x0 + lx, gy = y0 + ly;
@@ -182,6 +191,13 @@ __device__ __forceinline__ void stencil_tile(const P& pol, const Geom& g, int x0
       ++zi;
     }
   }
+}
+
+template <int R, int TY, class P>
+__device__ __forceinline__ void stencil_tile(const P& pol, const Geom& g, int x0, int y0,
+                                             int z0, int z1, typename P::Local& loc) {
+  __shared__ StencilLds<R, TY, P> sm;
+  stencil_tile<R, TY>(pol, g, x0, y0, z0, z1, loc, sm);
 }
 
 // Block sum of one double per thread; thread 0 writes it to *out.
