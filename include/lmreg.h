@@ -254,13 +254,18 @@ void lmr_pyramid_destroy(lmr_pyramid* pyr);
  * Box side 3..9 and Gaussian radius ceil(3 sigma) <= 4 are supported (else
  * LMR_EINVAL).  A barrier wait longer than 0.25 s (which means the blocks
  * were not all resident) makes every block leave; lmr_batch_sync reports it
- * as LMR_EHIP. */
+ * as LMR_EHIP.  The persistent launch needs all its blocks resident at once:
+ * kernels running at the same time on other streams (another batch's steps
+ * included) can hold the resources its last blocks wait for, so let such
+ * work finish first; a launch that cannot become resident times out as
+ * above instead of hanging. */
 typedef struct lmr_batch lmr_batch;
 lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes,
                             lmr_dtype img, const lmr_params* p);
 /* Starts every pair from the identity with lambda0[i] (NULL: 1.0).  fixed[i],
  * moving[i]: device images of pair i, which must stay valid while the batch
- * steps (the persistent kernel reads them through a device table). */
+ * steps (the persistent kernel reads them through a device table).  Returns
+ * after the batch stream has finished this work. */
 lmr_status lmr_batch_begin(lmr_batch* b, const void* const* fixed,
                            const void* const* moving, const double* lambda0);
 /* Enqueues n_iters iterations (one persistent launch each); use_graph = 1

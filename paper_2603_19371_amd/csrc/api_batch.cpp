@@ -213,6 +213,9 @@ lmr_status lmr_batch_begin(lmr_batch* b, const void* const* fixed,
   }
   LMR_HIP(hipMemcpyAsync(b->dev_pairs, b->host.data(), sizeof(BatchPair) * b->npairs,
                          hipMemcpyHostToDevice, b->stream));
+  // no begin kernel of this batch may still run when any batch's persistent
+  // launch needs the whole GPU
+  LMR_HIP(hipStreamSynchronize(b->stream));
   b->begun = true;
   return LMR_OK;
 }

@@ -39,8 +39,8 @@ struct BatchPair {
 // it is at, and no plain store to a counter has to be ordered against the
 // atomics of blocks on other chiplets.
 constexpr int kBarGroups = 8;
-// update work item: a 32 x 8 column (the staged update's tile) over 16 planes
-constexpr int kBatchUpdateTX = 32, kBatchUpdateTY = 8, kBatchUpdateCz = 16;
+// update work item: a 32 x 8 column (the staged update's tile) over 32 planes
+constexpr int kBatchUpdateTX = 32, kBatchUpdateTY = 8, kBatchUpdateCz = 32;
 struct BatchCtl {
   struct alignas(128) Line {
     unsigned long long v;
