@@ -56,11 +56,14 @@ lmr_status layout(lmr_batch* b) {
   for (int i = 0; i < b->npairs; ++i) {
     BatchPair& P = b->host[i];
     P.t = make_tiling(P.g.nz, P.g.ny, P.g.nx, ty, b->target_tiles, b->min_cz);
+    const int ucols = ((P.g.nx + kBatchUpdateTX - 1) / kBatchUpdateTX) *
+                      ((P.g.ny + kBatchUpdateTY - 1) / kBatchUpdateTY);
+    P.ucz = static_cast<int>(((long long)P.g.nz * ucols + kBatchUpdateItems - 1) /
+                             kBatchUpdateItems);
+    P.ucz = std::min(std::max(P.ucz, kBatchUpdateMinCz), kBatchUpdateMaxCz);
     P.utile0 = vox;
     P.tile0 = tiles;
-    vox += ((P.g.nx + kBatchUpdateTX - 1) / kBatchUpdateTX) *
-           ((P.g.ny + kBatchUpdateTY - 1) / kBatchUpdateTY) *
-           ((P.g.nz + kBatchUpdateCz - 1) / kBatchUpdateCz);
+    vox += ucols * ((P.g.nz + P.ucz - 1) / P.ucz);
     tiles += P.t.tiles();
   }
   b->n_update_items = vox;

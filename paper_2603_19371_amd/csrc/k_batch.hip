@@ -119,8 +119,8 @@ __global__ void __launch_bounds__(kNT)
     const int local = it - P.utile0;
     const int tx = (P.g.nx + kSX - 1) / kSX, ty = (P.g.ny + kSY - 1) / kSY;
     const int bx = (local % tx) * kSX, by = ((local / tx) % ty) * kSY;
-    const int z0 = (local / (tx * ty)) * kBatchUpdateCz;
-    const int z1 = min(z0 + kBatchUpdateCz, P.g.nz);
+    const int z0 = (local / (tx * ty)) * P.ucz;
+    const int z1 = min(z0 + P.ucz, P.g.nz);
     if (P.compositive) {
       staged_update_tile(static_cast<const T*>(P.M), P.g, a, bx, by, z0, z1, lds.upd);
     } else {

@@ -20,7 +20,8 @@ struct BatchPair {
   double* partials;  // one slot per stencil tile of this pair
   DevState* st;
   Tiling t;          // stencil tiling of this pair
-  int utile0;        // first update work item (32 x 8 x kBatchUpdateCz tile) of this pair
+  int utile0;        // first update work item of this pair
+  int ucz;           // planes per update work item of this pair
   int tile0;         // first stencil work item of this pair
   float eps;
   int compositive;
@@ -39,8 +40,11 @@ struct BatchPair {
 // it is at, and no plain store to a counter has to be ordered against the
 // atomics of blocks on other chiplets.
 constexpr int kBarGroups = 8;
-// update work item: a 32 x 8 column (the staged update's tile) over 32 planes
-constexpr int kBatchUpdateTX = 32, kBatchUpdateTY = 8, kBatchUpdateCz = 32;
+// update work item: a 32 x 8 column (the staged update's tile) over ucz
+// planes: about kBatchUpdateItems items per pair, 2..32 planes each (long
+// marches for large pairs, short ones where a pair has few columns)
+constexpr int kBatchUpdateTX = 32, kBatchUpdateTY = 8, kBatchUpdateItems = 256;
+constexpr int kBatchUpdateMinCz = 2, kBatchUpdateMaxCz = 32;
 struct BatchCtl {
   struct alignas(128) Line {
     unsigned long long v;
