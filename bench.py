@@ -52,7 +52,7 @@ def kernel_bytes(s):
     return {
         # g, u, M gather -> u~, warped M and its derivative (read by lncc_bwd)
         "update": 12 + 12 + s + 12 + 4 + 12,
-        "lncc_fwd": s + 4 + 16,              # F, warped M -> 4 adjoint maps
+        "lncc_fwd": s + 4 + 16 + 16,         # F, warped M, mu_F and sigma_FF -> 4 maps
         "decide": 0,
         "lncc_bwd": 16 + s + 4 + 12 + 12,    # maps, F, Mw, dMw -> g
         "smooth": 12 + 12,

@@ -121,14 +121,17 @@ void lmr_destroy(lmr_ctx* ctx);
 
 /* Starts a registration from `field` (device, [3][nz][ny][nx] FP32; NULL =
  * identity u = 0) with damping lambda0 > 0: evaluates L(u) and the smoothed
- * gradient of u.  fixed/moving: device images of the context's type. */
+ * gradient of u.  fixed/moving: device images of the context's type.  The
+ * window mean and variance of `fixed`, which no attempt changes, are computed
+ * here once and kept in the context. */
 lmr_status lmr_begin(lmr_ctx* ctx, const void* fixed, const void* moving,
                      const float* field, double lambda0);
 
 /* Enqueues n_attempts LM attempts (steps 1-5 above).  Each attempt reads the
  * accepted field, its smoothed gradient and (lambda, r) from device memory
  * and leaves the decision there; nothing returns to the host, so the calls
- * may be captured in a HIP graph.  A frozen pair skips its work.
+ * may be captured in a HIP graph.  A frozen pair skips its work.  `fixed`
+ * must hold the image given to lmr_begin (its window statistics are reused).
  * Errors: LMR_ESTATE before lmr_begin. */
 lmr_status lmr_step(lmr_ctx* ctx, const void* fixed, const void* moving,
                     int n_attempts);

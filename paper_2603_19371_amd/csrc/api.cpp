@@ -63,7 +63,7 @@ lmr_status enqueue_attempt(lmr_ctx* c, const void* F, const void* M, int force) 
                         nullptr, 0.0, 0.0, c->Mw, c->graw, s));
   LMR_HIP(mark(LMR_K_UPDATE, 1));
   LMR_HIP(mark(LMR_K_FWD, 0));
-  LMR_HIP(launch_fwd(F, c->img, c->Mw, c->g, c->p, c->st, c->maps, c->partials,
+  LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, c->st, c->maps, c->partials,
                      nullptr, s));
   LMR_HIP(mark(LMR_K_FWD, 1));
   LMR_HIP(mark(LMR_K_DECIDE, 0));
@@ -152,7 +152,8 @@ lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
                           align256(sizeof(double)),
                           align256(sizeof(DevState)),
                           align256(sizeof(double)),
-                          align256(sizeof(unsigned long long))};
+                          align256(sizeof(unsigned long long)),
+                          align256(sizeof(double) * 2 * N)};
   size_t total = 0;
   for (size_t s : sizes) total += s;
   hipError_t e = hipMalloc(&c->arena, total);
@@ -174,6 +175,7 @@ lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
   c->st_probe = reinterpret_cast<DevState*>(q); q += sizes[9];
   c->part_probe = reinterpret_cast<double*>(q); q += sizes[10];
   c->counter = reinterpret_cast<unsigned long long*>(q);
+  c->fstat = reinterpret_cast<double*>(q + sizes[11]);
   c->begun = false;
   *out = c;
   return LMR_OK;
@@ -196,9 +198,10 @@ lmr_status lmr_begin(lmr_ctx* c, const void* F, const void* M, const float* fiel
     LMR_HIP(hipMemcpyAsync(c->U[0], field, bytes, hipMemcpyDeviceToDevice, s));
   else
     LMR_HIP(launch_fill(c->U[0], 3 * c->g.N, 0.0f, s));
+  LMR_HIP(launch_fstat(F, c->img, c->g, c->p, c->fstat, s));
   LMR_HIP(launch_warp(M, c->img, c->U[0], c->g, c->Mw, nullptr, s));
-  LMR_HIP(launch_fwd(F, c->img, c->Mw, c->g, c->p, nullptr, c->maps, c->partials,
-                     nullptr, s));
+  LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, nullptr, c->maps,
+                     c->partials, nullptr, s));
   LMR_HIP(launch_decide(c->st, c->partials, c->nparts, c->g.N, c->dp, 1, -1, lambda0,
                         nullptr, s));
   LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, nullptr, nullptr,
@@ -287,9 +290,11 @@ lmr_status lmr_loss_grad(lmr_ctx* c, const void* F, const void* M, const float* 
                          float* cc_map) {
   if (!c || !F || !M || !u) return LMR_EINVAL;
   hipStream_t s = c->stream;
+  // a stage call may pass any fixed image: its statistics are taken here
+  LMR_HIP(launch_fstat(F, c->img, c->g, c->p, c->fstat, s));
   LMR_HIP(launch_warp(M, c->img, u, c->g, c->Mw, nullptr, s));
-  LMR_HIP(launch_fwd(F, c->img, c->Mw, c->g, c->p, nullptr, c->maps, c->partials,
-                     cc_map, s));
+  LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, nullptr, c->maps,
+                     c->partials, cc_map, s));
   LMR_HIP(launch_decide(c->st, c->partials, c->nparts, c->g.N, c->dp, 2, -1, 0.0,
                         c->probe, s));
   if (g_raw || g_smooth) {

@@ -186,6 +186,7 @@ lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes, lmr_
     P.graw = c->graw;
     P.maps = c->maps;
     P.Mw = c->Mw;
+    P.fstat = c->fstat;
     P.partials = b->partials[i];
     P.st = c->st;
     P.eps = static_cast<float>(p->step_eps);

@@ -30,6 +30,7 @@ struct lmr_ctx {
   float* graw;
   float* maps;
   float* Mw;
+  double* fstat;  // window mean and variance of the fixed image [2][N]
   double* partials;
   int nparts;
   lmr::DevState* st;

@@ -139,6 +139,7 @@ __global__ void __launch_bounds__(kNT)
     FwdPol<T, kNT> pol;
     pol.F = static_cast<const T*>(P.F);
     pol.Mw = P.Mw;
+    pol.fstat = P.fstat;
     pol.maps = P.maps;
     pol.cc = nullptr;
     pol.partials = P.partials;

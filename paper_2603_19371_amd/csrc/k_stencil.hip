@@ -49,12 +49,24 @@ hipError_t run_box(const P& pol, int window, const Geom& g, const DevState* st, 
 }
 
 template <typename T>
-hipError_t fwd_t(const T* F, const float* Mw, const Geom& g, const lmr_params& p,
-                 const DevState* st, float* maps, double* partials, float* cc,
-                 hipStream_t s) {
+hipError_t fstat_t(const T* F, const Geom& g, const lmr_params& p, double* fstat,
+                   hipStream_t s) {
+  FStatPol<T> pol;
+  pol.F = F;
+  pol.fstat = fstat;
+  pol.N = static_cast<int>(g.N);
+  pol.inv_n = 1.0 / ((double)p.window * p.window * p.window);
+  return run_box(pol, p.window, g, nullptr, 0, s);
+}
+
+template <typename T>
+hipError_t fwd_t(const T* F, const float* Mw, const double* fstat, const Geom& g,
+                 const lmr_params& p, const DevState* st, float* maps, double* partials,
+                 float* cc, hipStream_t s) {
   FwdPol<T, kTX * kTY> pol;
   pol.F = F;
   pol.Mw = Mw;
+  pol.fstat = fstat;
   pol.maps = maps;
   pol.cc = cc;
   pol.partials = partials;
@@ -104,13 +116,20 @@ int gauss_radius(double sigma) {
   return (int)ceil(3.0 * sigma - 1e-12);
 }
 
-hipError_t launch_fwd(const void* F, lmr_dtype t, const float* Mw, const Geom& g,
-                      const lmr_params& p, const DevState* st, float* maps,
+hipError_t launch_fstat(const void* F, lmr_dtype t, const Geom& g, const lmr_params& p,
+                        double* fstat, hipStream_t s) {
+  if (t == LMR_BF16) return fstat_t(static_cast<const uint16_t*>(F), g, p, fstat, s);
+  return fstat_t(static_cast<const float*>(F), g, p, fstat, s);
+}
+
+hipError_t launch_fwd(const void* F, lmr_dtype t, const float* Mw, const double* fstat,
+                      const Geom& g, const lmr_params& p, const DevState* st, float* maps,
                       double* partials, float* cc_map, hipStream_t s) {
   if (t == LMR_BF16)
-    return fwd_t(static_cast<const uint16_t*>(F), Mw, g, p, st, maps, partials, cc_map,
-                 s);
-  return fwd_t(static_cast<const float*>(F), Mw, g, p, st, maps, partials, cc_map, s);
+    return fwd_t(static_cast<const uint16_t*>(F), Mw, fstat, g, p, st, maps, partials,
+                 cc_map, s);
+  return fwd_t(static_cast<const float*>(F), Mw, fstat, g, p, st, maps, partials, cc_map,
+               s);
 }
 
 hipError_t launch_bwd(const void* F, const void* M, lmr_dtype t, const float* Mw,

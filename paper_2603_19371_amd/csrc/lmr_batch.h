@@ -17,6 +17,7 @@ struct BatchPair {
   float* graw;
   float* maps;
   float* Mw;
+  const double* fstat;  // window mean and variance of F (the pair context's)
   double* partials;  // one slot per stencil tile of this pair
   DevState* st;
   Tiling t;          // stencil tiling of this pair

@@ -335,9 +335,13 @@ hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
                          const float* G, float* U0, float* U1, const float* u_in,
                          float* u_out, double r, double lambda, float* Mw, float* dMw,
                          hipStream_t s);
+// Window mean and variance of F (FP64, [2][N]), read by every P2 on that F.
+hipError_t launch_fstat(const void* F, lmr_dtype t, const Geom& g, const lmr_params& p,
+                        double* fstat, hipStream_t s);
 // P2: LNCC forward; writes adjoint maps, per-block partials and optionally cc.
-hipError_t launch_fwd(const void* F, lmr_dtype t, const float* Mw, const Geom& g,
-                      const lmr_params& p, const DevState* st, float* maps,
+// fstat: launch_fstat's output for the same F.
+hipError_t launch_fwd(const void* F, lmr_dtype t, const float* Mw, const double* fstat,
+                      const Geom& g, const lmr_params& p, const DevState* st, float* maps,
                       double* partials, float* cc_map, hipStream_t s);
 // P3: FP64 reduction of the partials and the decision.
 // mode 0: attempt (force -1/0/1), mode 1: begin (lambda0), mode 2: probe.

@@ -2,8 +2,9 @@
 // device functions used by the per-pair kernels (k_stencil.hip) and by the
 // batched persistent kernel (k_batch.hip).
 //
-//   FwdPol    LNCC forward: box sums of F, Mw, F^2, Mw^2, F Mw over the w^3
-//             window (zero padding, divisor w^3), cc = s_FM^2/(s_FF s_MM + eps),
+//   FStatPol  window mean and variance of F, once per pair.
+//   FwdPol    LNCC forward: box sums of Mw, Mw^2, F Mw over the w^3 window
+//             (zero padding, divisor w^3), cc = s_FM^2/(s_FF s_MM + eps),
 //             adjoint maps alpha = 2 s_FM/D, alpha mu_F, beta = -s_FM^2 s_FF/D^2,
 //             beta mu_M, and one FP64 partial sum of cc per tile.
 //   BwdPol    LNCC backward: box sums of the four maps give
@@ -218,14 +219,50 @@ __device__ __forceinline__ void block_sum_to(double v, double* out) {
   __syncthreads();
 }
 
+// ------------------------------------------------- statistics of F (once)
+// The window mean and variance of the fixed image do not change between
+// attempts: they are box-summed once per pair (at begin) and stored in FP64
+// as mu_F and sigma_FF, from sums of the exact products F^2.
+template <typename T>
+struct FStatPol {
+  using Acc = double;
+  static constexpr int NRAW = 1, NCH = 2;
+  static constexpr bool kBox = true;
+  const T* __restrict__ F;
+  double* __restrict__ fstat;  // [2][N]: mu_F, sigma_FF
+  int N;
+  double inv_n;
+  struct Local {
+    RBuf bF;
+  };
+
+  __device__ static constexpr double wt(int) { return 1.0; }
+  __device__ Local begin_block(const DevState*) const { return Local{make_rbuf_n(F, N)}; }
+  __device__ void load(const Local& l, unsigned i, float v[1]) const { v[0] = bld<T>(l.bF, i); }
+  __device__ void accum(double a[2], const float r[1], int) const {
+    const double f = r[0];
+    a[0] += f;
+    a[1] = fma(f, f, a[1]);
+  }
+  __device__ void emit(Local&, int i, int, int, int, const double S[2]) const {
+    const double muF = S[0] * inv_n;
+    fstat[i] = muF;
+    fstat[N + i] = S[1] * inv_n - muF * muF;
+  }
+  __device__ void end_tile(Local&, int) const {}
+};
+
 // ------------------------------------------------------------- forward (P2)
+// Box sums of Mw, Mw^2 and F Mw (exact products in FP64); mu_F and sigma_FF
+// come from FStatPol's pass over the same F.
 template <typename T, int NT>
 struct FwdPol {
   using Acc = double;
-  static constexpr int NRAW = 2, NCH = 5;
+  static constexpr int NRAW = 2, NCH = 3;
   static constexpr bool kBox = true;
   const T* __restrict__ F;
   const float* __restrict__ Mw;
+  const double* __restrict__ fstat;
   float* __restrict__ maps;
   float* __restrict__ cc;
   double* __restrict__ partials;
@@ -244,19 +281,17 @@ struct FwdPol {
     v[0] = bld<T>(l.bF, i);
     v[1] = bld<float>(l.bM, i);
   }
-  __device__ void accum(double a[5], const float r[2], int) const {
+  __device__ void accum(double a[3], const float r[2], int) const {
     const double f = r[0], m = r[1];
-    a[0] += f;
-    a[1] += m;
-    a[2] = fma(f, f, a[2]);
-    a[3] = fma(m, m, a[3]);
-    a[4] = fma(f, m, a[4]);
+    a[0] += m;
+    a[1] = fma(m, m, a[1]);
+    a[2] = fma(f, m, a[2]);
   }
-  __device__ void emit(Local& loc, int i, int, int, int, const double S[5]) const {
-    const double muF = S[0] * inv_n, muM = S[1] * inv_n;
-    const double sfm = S[4] * inv_n - muF * muM;
-    const double sff = S[2] * inv_n - muF * muF;
-    const double smm = S[3] * inv_n - muM * muM;
+  __device__ void emit(Local& loc, int i, int, int, int, const double S[3]) const {
+    const double muF = fstat[i], sff = fstat[N + i];
+    const double muM = S[0] * inv_n;
+    const double sfm = S[2] * inv_n - muF * muM;
+    const double smm = S[1] * inv_n - muM * muM;
     const double iD = 1.0 / (sff * smm + eps);
     const double c = sfm * sfm * iD;
     const double alpha = 2.0 * sfm * iD;
