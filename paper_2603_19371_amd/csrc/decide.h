@@ -26,22 +26,35 @@ template <int NT>
 __device__ void decide_block(DevState* st, const double* __restrict__ partials,
                              int nparts, long long N, const DecideParams& dp, int mode,
                              int force, double lambda0, double* probe) {
+  static_assert(NT >= 64 && (NT & (NT - 1)) == 0, "power-of-two block of whole waves");
   __shared__ double sh[NT];
   __shared__ int skip;
-  if (threadIdx.x == 0) skip = (mode == 0 && st->stalled) ? 1 : 0;
+  // thread 0 fetches the state while the partials are being loaded
+  DevState cur_st;
+  if (threadIdx.x == 0) {
+    cur_st = *st;
+    skip = (mode == 0 && cur_st.stalled) ? 1 : 0;
+  }
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += NT) s += partials[k];
+  sh[threadIdx.x] = s;
   __syncthreads();
   if (skip) {
     if (threadIdx.x == 0) st->accepted = 0;
     __syncthreads();
     return;
   }
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nparts; k += NT) s += partials[k];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = NT / 2; w > 0; w >>= 1) {
+  // the fixed tree sh[t] += sh[t + w], w = NT/2 ... 1: the steps across waves
+  // in LDS, the last six inside wave 0 with the same operands and order
+  for (int w = NT / 2; w >= 64; w >>= 1) {
     if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
+  }
+  if (threadIdx.x < 64) {
+    double v = sh[threadIdx.x];
+#pragma unroll
+    for (int w = 32; w > 0; w >>= 1) v += __shfl_down(v, w, 64);
+    if (threadIdx.x == 0) sh[0] = v;
   }
   if (threadIdx.x == 0) {
     const double L = -sh[0] / static_cast<double>(N);
@@ -60,8 +73,10 @@ __device__ void decide_block(DevState* st, const double* __restrict__ partials,
       st->cur = 0;
       st->attempts = 0;
     } else {
-      st->cand_loss = L;
-      st->attempts += 1;
+      // the decision on the state read at entry; the new state is written back
+      DevState n = cur_st;
+      n.cand_loss = L;
+      n.attempts += 1;
       int acc;
       if (force >= 0) {
         acc = force ? 1 : 0;
@@ -70,24 +85,25 @@ __device__ void decide_block(DevState* st, const double* __restrict__ partials,
       } else if (dp.tau < 0.0) {
         acc = 1;
       } else {
-        const double ref = st->n_hist >= 2 ? fabs(st->loss - st->loss_prev) : 0.0;
-        acc = !((L - st->loss) > dp.tau * ref);
+        const double ref = n.n_hist >= 2 ? fabs(n.loss - n.loss_prev) : 0.0;
+        acc = !((L - n.loss) > dp.tau * ref);
       }
       if (acc) {
-        const double f = (L > st->loss) ? dp.lambda_inc : dp.lambda_dec;
-        st->lambda = clamp_d(f * st->lambda, dp.lambda_min, dp.lambda_max);
-        st->loss_prev = st->loss;
-        st->loss = L;
-        st->r = 1.0 + L;
-        st->n_hist += 1;
-        st->retries = 0;
-        st->cur = 1 - st->cur;
+        const double f = (L > n.loss) ? dp.lambda_inc : dp.lambda_dec;
+        n.lambda = clamp_d(f * n.lambda, dp.lambda_min, dp.lambda_max);
+        n.loss_prev = n.loss;
+        n.loss = L;
+        n.r = 1.0 + L;
+        n.n_hist += 1;
+        n.retries = 0;
+        n.cur = 1 - n.cur;
       } else {
-        st->lambda = clamp_d(dp.lambda_inc * st->lambda, dp.lambda_min, dp.lambda_max);
-        st->retries += 1;
-        if (st->retries >= dp.max_retries && st->lambda >= dp.lambda_max) st->stalled = 1;
+        n.lambda = clamp_d(dp.lambda_inc * n.lambda, dp.lambda_min, dp.lambda_max);
+        n.retries += 1;
+        if (n.retries >= dp.max_retries && n.lambda >= dp.lambda_max) n.stalled = 1;
       }
-      st->accepted = acc;
+      n.accepted = acc;
+      *st = n;
     }
   }
   __syncthreads();
