@@ -164,6 +164,16 @@ def _pyramid_line(a, F, M, img_dtype, factors, iters, workload, s):
             attempt_bytes(s) * nfine / (attempt_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernel_source_sha": source_sha(),
     }
+    # measured HBM bytes of a whole attempt (rocprofv3 counters of each kernel,
+    # per launch, averaged over accepted and rejected attempts like the
+    # durations) over the attempt's kernel time, while the counters match the
+    # current sources
+    moved = {k: traffic_for(k, workload) for k in ("update", "lncc_fwd", "lncc_bwd", "smooth")}
+    if all(v is not None for v in moved.values()):
+        t_ms = sum(prof[k]["avg_ms"] for k in moved if prof[k]["count"])
+        b = sum(moved.values())
+        detail["fine_level_attempt_hbm_bytes_per_voxel"] = round(b / nfine, 1)
+        detail["fine_level_attempt_hbm_frac"] = round(b / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     return vox_att * a.steps / elapsed, elapsed, vox_att, roofline, detail
 
 
