@@ -236,8 +236,10 @@ def run_batch(a):
     Fs = [p[0] for p in pairs]
     Ms = [p[1] for p in pairs]
     b = _lib.Batch(BATCH_SHAPES, window=WINDOW, grad_sigma=SIGMA)
-    cache = os.path.join(ROOT, "gpurun_out", "batch_tune.txt")
-    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    # autotuner cache: per machine, outside the source tree
+    import tempfile
+    cache = os.environ.get("LMR_TUNE_CACHE",
+                           os.path.join(tempfile.gettempdir(), "lmr_batch_tune.txt"))
     tune_ms = b.tune(Fs, Ms, cache_path=cache, iters=3)
     cfg = b.config()
     for _ in range(a.warmup):
@@ -290,8 +292,8 @@ def main():
     ap.add_argument("--workload", choices=("brain", "lung", "batch"), default="brain")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the registration of one pair runs on one device).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(one pair's registration runs on one device).", file=sys.stderr)
         sys.exit(2)
 
     run = {"brain": run_brain, "lung": run_lung, "batch": run_batch}[a.workload]
