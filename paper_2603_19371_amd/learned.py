@@ -2,9 +2,9 @@
 predicts an initial displacement; LM refines from it and stays the fallback.
 
     python -m paper_2603_19371_amd.learned train --pairs 2000 --epochs 4 \\
-        --out gpurun_out/unet.npy
-    python -m paper_2603_19371_amd.learned eval --weights gpurun_out/unet.npy \\
-        --seeds 5000:5200 --out gpurun_out/eval.json
+        --out unet.npy
+    python -m paper_2603_19371_amd.learned eval --weights unet.npy \\
+        --seeds 5000:5200 --out eval.json
 
 Pipeline (full-resolution pair of shape S, network at S/2):
   1. the network sees (F, M) average-pooled by 2 and predicts a field in
