@@ -257,6 +257,32 @@ __device__ __forceinline__ void bcorners(const RBuf& b, const Geom&, const BCell
     v[2 * q + 1] = bld<T>(b, c.r[q] + c.xb);
   }
 }
+// BF16 volumes with an even row length of at least 4: the two corners of a
+// row come from one 8-byte load of four elements starting at the even
+// index min(xc & ~1, nx - 4) (4-byte aligned, never past the row end), which
+// holds both clamped corners xa and xb.
+template <>
+__device__ __forceinline__ void bcorners<uint16_t>(const RBuf& b, const Geom& g,
+                                                   const BCell& c, float v[8]) {
+  if ((g.nx & 1) || g.nx < 4) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[2 * q] = bld<uint16_t>(b, c.r[q] + c.xa);
+      v[2 * q + 1] = bld<uint16_t>(b, c.r[q] + c.xb);
+    }
+    return;
+  }
+  const unsigned base = min(c.xc & ~1u, static_cast<unsigned>(g.nx - 4));
+  const unsigned sa = 16u * (c.xa - base), sb = 16u * (c.xb - base);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const auto p = __builtin_amdgcn_raw_buffer_load_b64(b.r, (c.r[q] + base) * 2u, 0, 0);
+    const unsigned long long w =
+        (static_cast<unsigned long long>(p[1]) << 32) | static_cast<unsigned long long>(p[0]);
+    v[2 * q] = __uint_as_float(static_cast<uint32_t>((w >> sa) & 0xFFFFu) << 16);
+    v[2 * q + 1] = __uint_as_float(static_cast<uint32_t>((w >> sb) & 0xFFFFu) << 16);
+  }
+}
 template <>
 __device__ __forceinline__ void bcorners<float>(const RBuf& b, const Geom& g, const BCell& c,
                                                 float v[8]) {

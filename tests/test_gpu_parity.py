@@ -176,6 +176,23 @@ def test_gathers_at_volume_corners(L, orc, sign):
     assert e < 2e-6, e
 
 
+@pytest.mark.parametrize("nx", [12, 11, 4])
+def test_bf16_gathers_at_row_ends(L, orc, nx):
+    """BF16 images: even rows of four or more elements take both corners of a
+    row from one 8-byte load (clamped at the row end), odd rows one load per
+    corner; displacements reach past both ends of every axis."""
+    from paper_2603_19371_amd.phantoms import bf16_to_f32, to_bf16_rne
+    shape = (9, 10, nx)
+    rng = np.random.default_rng(41 + nx)
+    M = bf16_to_f32(to_bf16_rne(rng.uniform(0.5, 1.5, shape).astype(np.float32)))
+    for u in (rng.uniform(-3, 3, (3,) + shape).astype(np.float32),
+              np.full((3,) + shape, 0.3, np.float32), np.full((3,) + shape, -0.3, np.float32)):
+        got, dgot = L.warp(dev(M, torch.bfloat16), dev(u), with_grad=True)
+        ref, dref = orc.warp(M, u, with_grad=True)
+        e, de = np.abs(host(got) - ref).max(), np.abs(host(dgot) - dref).max()
+        assert e < 1e-6 and de < 1e-5, (nx, e, de)
+
+
 # Large enough for the LDS-staged form of the update (ragged in x, y and in
 # the last z-chunk).  With the smaller gradients most steps go beyond one
 # voxel, where the gather falls back to memory; with the larger none do.
