@@ -72,17 +72,16 @@ struct StencilLds {
 };
 
 // Runs the stencil over tile (x0, y0, z0..z1) with the whole block, in the
-// LDS `sm` (a kernel that runs several phases can overlay their LDS).
+// LDS arrays s_in (staged raw inputs) and s_y (y-pass sums).
 template <int R, int TY, class P>
-__device__ __forceinline__ void stencil_tile(const P& pol, const Geom& g, int x0, int y0,
-                                             int z0, int z1, typename P::Local& loc,
-                                             StencilLds<R, TY, P>& sm) {
+__device__ __forceinline__ void stencil_tile_in(
+    const P& pol, const Geom& g, int x0, int y0, int z0, int z1, typename P::Local& loc,
+    float (&s_in)[P::NRAW][TY + 2 * R][kTX + 2 * R],
+    typename P::Acc (&s_y)[P::NCH][TY][kTX + 2 * R]) {
   using A = typename P::Acc;
   constexpr int NR = P::NRAW, NC = P::NCH;
   constexpr int W = 2 * R + 1, LX = kTX + 2 * R, LY = TY + 2 * R, NT = kTX * TY;
   constexpr int NPOS = LX * LY, PER = (NPOS + NT - 1) / NT;
-  auto& s_in = sm.in;
-  auto& s_y = sm.y;
 
   const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
   const int gx = x0 + lx, gy = y0 + ly;
@@ -194,11 +193,28 @@ __device__ __forceinline__ void stencil_tile(const P& pol, const Geom& g, int x0
   }
 }
 
+// In the LDS `sm` (a kernel that runs several phases overlays their LDS).
+template <int R, int TY, class P>
+__device__ __forceinline__ void stencil_tile(const P& pol, const Geom& g, int x0, int y0,
+                                             int z0, int z1, typename P::Local& loc,
+                                             StencilLds<R, TY, P>& sm) {
+  stencil_tile_in<R, TY>(pol, g, x0, y0, z0, z1, loc, sm.in, sm.y);
+}
+
+// In LDS of its own.  Both forms give the same results; the compiler
+// schedules them differently, and the backward pass runs faster with two
+// separate arrays, the others with one struct (measured).
 template <int R, int TY, class P>
 __device__ __forceinline__ void stencil_tile(const P& pol, const Geom& g, int x0, int y0,
                                              int z0, int z1, typename P::Local& loc) {
-  __shared__ StencilLds<R, TY, P> sm;
-  stencil_tile<R, TY>(pol, g, x0, y0, z0, z1, loc, sm);
+  if constexpr (P::kSeparateLds) {
+    __shared__ float s_in[P::NRAW][TY + 2 * R][kTX + 2 * R];
+    __shared__ typename P::Acc s_y[P::NCH][TY][kTX + 2 * R];
+    stencil_tile_in<R, TY>(pol, g, x0, y0, z0, z1, loc, s_in, s_y);
+  } else {
+    __shared__ StencilLds<R, TY, P> sm;
+    stencil_tile_in<R, TY>(pol, g, x0, y0, z0, z1, loc, sm.in, sm.y);
+  }
 }
 
 // Block sum of one double per thread; thread 0 writes it to *out.
@@ -227,7 +243,7 @@ template <typename T>
 struct FStatPol {
   using Acc = double;
   static constexpr int NRAW = 1, NCH = 2;
-  static constexpr bool kBox = true;
+  static constexpr bool kBox = true, kSeparateLds = false;
   const T* __restrict__ F;
   double* __restrict__ fstat;  // [2][N]: mu_F, sigma_FF
   int N;
@@ -259,7 +275,7 @@ template <typename T, int NT>
 struct FwdPol {
   using Acc = double;
   static constexpr int NRAW = 2, NCH = 3;
-  static constexpr bool kBox = true;
+  static constexpr bool kBox = true, kSeparateLds = false;
   const T* __restrict__ F;
   const float* __restrict__ Mw;
   const double* __restrict__ fstat;
@@ -315,7 +331,7 @@ template <typename T>
 struct BwdPol {
   using Acc = double;
   static constexpr int NRAW = 4, NCH = 4;
-  static constexpr bool kBox = true;
+  static constexpr bool kBox = true, kSeparateLds = true;
   const T* __restrict__ F;
   const T* __restrict__ M;
   const float* __restrict__ Mw;
@@ -384,7 +400,7 @@ template <int R>
 struct SmoothPol {
   using Acc = float;
   static constexpr int NRAW = 3, NCH = 3;
-  static constexpr bool kBox = false;
+  static constexpr bool kBox = false, kSeparateLds = false;
   const float* __restrict__ in;
   float* __restrict__ out;
   int N;
