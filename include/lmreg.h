@@ -130,8 +130,10 @@ lmr_status lmr_begin(lmr_ctx* ctx, const void* fixed, const void* moving,
 /* Enqueues n_attempts LM attempts (steps 1-5 above).  Each attempt reads the
  * accepted field, its smoothed gradient and (lambda, r) from device memory
  * and leaves the decision there; nothing returns to the host, so the calls
- * may be captured in a HIP graph.  A frozen pair skips its work.  `fixed`
- * must hold the image given to lmr_begin (its window statistics are reused).
+ * may be captured in a HIP graph.  A frozen pair skips its work.  The window
+ * statistics of `fixed` are reused from lmr_begin while the same buffer is
+ * passed (another buffer makes the call recompute them first; contents
+ * changed in place need a new lmr_begin).
  * Errors: LMR_ESTATE before lmr_begin. */
 lmr_status lmr_step(lmr_ctx* ctx, const void* fixed, const void* moving,
                     int n_attempts);

@@ -199,6 +199,7 @@ lmr_status lmr_begin(lmr_ctx* c, const void* F, const void* M, const float* fiel
   else
     LMR_HIP(launch_fill(c->U[0], 3 * c->g.N, 0.0f, s));
   LMR_HIP(launch_fstat(F, c->img, c->g, c->p, c->fstat, s));
+  c->fstat_of = F;
   LMR_HIP(launch_warp(M, c->img, c->U[0], c->g, c->Mw, nullptr, s));
   LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, nullptr, c->maps,
                      c->partials, nullptr, s));
@@ -211,9 +212,23 @@ lmr_status lmr_begin(lmr_ctx* c, const void* F, const void* M, const float* fiel
   return LMR_OK;
 }
 
+// The statistics of F are kept from lmr_begin; a step given another fixed
+// image buffer recomputes them first (an image rewritten in place is the
+// caller's to avoid, as documented).
+static lmr_status refresh_fstat(lmr_ctx* c, const void* F) {
+  if (F == c->fstat_of) return LMR_OK;
+  LMR_HIP(launch_fstat(F, c->img, c->g, c->p, c->fstat, c->stream));
+  c->fstat_of = F;
+  return LMR_OK;
+}
+
 lmr_status lmr_step(lmr_ctx* c, const void* F, const void* M, int n) {
   if (!c || !F || !M || n < 0) return LMR_EINVAL;
   if (!c->begun) return LMR_ESTATE;
+  if (n > 0) {
+    const lmr_status r = refresh_fstat(c, F);
+    if (r != LMR_OK) return r;
+  }
   for (int i = 0; i < n; ++i) {
     lmr_status r = enqueue_attempt(c, F, M, -1);
     if (r != LMR_OK) return r;
@@ -225,6 +240,10 @@ lmr_status lmr_step_forced(lmr_ctx* c, const void* F, const void* M,
                            const int* decisions, int n) {
   if (!c || !F || !M || n < 0 || (n > 0 && !decisions)) return LMR_EINVAL;
   if (!c->begun) return LMR_ESTATE;
+  if (n > 0) {
+    const lmr_status r = refresh_fstat(c, F);
+    if (r != LMR_OK) return r;
+  }
   for (int i = 0; i < n; ++i) {
     int d = decisions[i] < 0 ? -1 : (decisions[i] ? 1 : 0);
     lmr_status r = enqueue_attempt(c, F, M, d);
@@ -292,6 +311,7 @@ lmr_status lmr_loss_grad(lmr_ctx* c, const void* F, const void* M, const float* 
   hipStream_t s = c->stream;
   // a stage call may pass any fixed image: its statistics are taken here
   LMR_HIP(launch_fstat(F, c->img, c->g, c->p, c->fstat, s));
+  c->fstat_of = F;
   LMR_HIP(launch_warp(M, c->img, u, c->g, c->Mw, nullptr, s));
   LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, nullptr, c->maps,
                      c->partials, cc_map, s));

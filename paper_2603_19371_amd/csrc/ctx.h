@@ -31,6 +31,7 @@ struct lmr_ctx {
   float* maps;
   float* Mw;
   double* fstat;  // window mean and variance of the fixed image [2][N]
+  const void* fstat_of;  // the fixed image fstat was computed from
   double* partials;
   int nparts;
   lmr::DevState* st;

@@ -420,6 +420,22 @@ def test_run_is_bitwise_deterministic(L):
     assert outs[0][1] == outs[1][1]
 
 
+def test_fixed_image_statistics_follow_the_buffer(L):
+    """The window statistics of F come from lmr_begin while the step gets the
+    same buffer, and are recomputed when it gets another one: both runs are
+    bitwise equal when the buffers hold the same image."""
+    ph = _config1(2)
+    outs = []
+    for same in (True, False):
+        ctx = L.Context(ph.F.shape, window=5)
+        F0, Md = dev(ph.F), dev(ph.M)
+        ctx.begin(F0, Md)
+        ctx.step(F0 if same else dev(ph.F), Md, 10)
+        outs.append((host(ctx.field()), ctx.state()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]
+
+
 def test_stalled_pair_is_frozen(L):
     ph = _config1(3)
     ctx = L.Context(ph.F.shape, window=5, lambda_max=4.0, max_retries=2)
