@@ -60,10 +60,12 @@ typedef enum {
 
 typedef enum { LMR_F32 = 0, LMR_BF16 = 1 } lmr_dtype;
 
-/* Accumulator of the LNCC box sums.  LMR_ACC_F64: exact FP32 products summed
- * in FP64 (default: on gfx950 an FP64 add issues at the rate of an unpacked
- * FP32 add).  LMR_ACC_F32C: FP32 hi/lo pairs with error-free TwoSum/TwoProd
- * (compensated FP32). */
+/* Accumulator of the LNCC box sums (forward, backward and the fixed image's
+ * statistics).  LMR_ACC_F64: exact FP32 products summed in FP64 (default: on
+ * gfx950 an FP64 add issues at the rate of an unpacked FP32 add).
+ * LMR_ACC_F32C: compensated FP32, sums kept as normalised hi/lo float pairs
+ * with TwoSum additions and exact FMA products; the window statistics are then
+ * formed in FP64 from hi + lo.  The batched form takes LMR_ACC_F64 only. */
 typedef enum { LMR_ACC_F64 = 0, LMR_ACC_F32C = 1 } lmr_accum;
 
 /* Hyper-parameters of one registration.  The paper's own setting

@@ -32,7 +32,7 @@ bool lmr::params_ok(const lmr_params* p) {
   if (!(p->grad_sigma >= 0.0 && p->grad_sigma <= 2.0)) return false;
   if (!(p->cc_eps >= 0.0)) return false;
   if (!(p->step_eps > 0.0)) return false;
-  if (p->accum != LMR_ACC_F64) return false;
+  if (p->accum != LMR_ACC_F64 && p->accum != LMR_ACC_F32C) return false;
   if (!(p->lambda_inc > 1.0) || !(p->lambda_dec > 0.0 && p->lambda_dec < 1.0)) return false;
   if (!(p->lambda_min > 0.0) || !(p->lambda_max >= p->lambda_min)) return false;
   if (p->max_retries < 1) return false;

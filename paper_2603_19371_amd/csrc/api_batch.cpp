@@ -124,6 +124,7 @@ lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes, lmr_
   if (!out || npairs < 1 || npairs > 4096 || !shapes) return LMR_EINVAL;
   *out = nullptr;
   if (!params_ok(p) || (img != LMR_F32 && img != LMR_BF16)) return LMR_EINVAL;
+  if (p->accum != LMR_ACC_F64) return LMR_EINVAL;  // the persistent kernel sums in FP64
   const int rb = p->window / 2, rg = gauss_r(p->grad_sigma);
   const void* kernel = batch_kernel(img, rb, rg);
   if (!kernel) return LMR_EINVAL;  // Gaussian radius beyond the instantiated range

@@ -48,10 +48,10 @@ hipError_t run_box(const P& pol, int window, const Geom& g, const DevState* st, 
   }
 }
 
-template <typename T>
+template <typename T, typename Acc>
 hipError_t fstat_t(const T* F, const Geom& g, const lmr_params& p, double* fstat,
                    hipStream_t s) {
-  FStatPol<T> pol;
+  FStatPol<T, Acc> pol;
   pol.F = F;
   pol.fstat = fstat;
   pol.N = static_cast<int>(g.N);
@@ -59,11 +59,11 @@ hipError_t fstat_t(const T* F, const Geom& g, const lmr_params& p, double* fstat
   return run_box(pol, p.window, g, nullptr, 0, s);
 }
 
-template <typename T>
+template <typename T, typename Acc>
 hipError_t fwd_t(const T* F, const float* Mw, const double* fstat, const Geom& g,
                  const lmr_params& p, const DevState* st, float* maps, double* partials,
                  float* cc, hipStream_t s) {
-  FwdPol<T, kTX * kTY> pol;
+  FwdPol<T, kTX * kTY, Acc> pol;
   pol.F = F;
   pol.Mw = Mw;
   pol.fstat = fstat;
@@ -76,12 +76,12 @@ hipError_t fwd_t(const T* F, const float* Mw, const double* fstat, const Geom& g
   return run_box(pol, p.window, g, st, 1, s);
 }
 
-template <typename T>
+template <typename T, typename Acc>
 hipError_t bwd_t(const T* F, const T* M, const float* Mw, const float* maps,
                  const Geom& g, const lmr_params& p, const DevState* st,
                  const float* U0, const float* U1, const float* ue, const float* dMw,
                  float* graw, hipStream_t s) {
-  BwdPol<T> pol;
+  BwdPol<T, Acc> pol;
   pol.F = F;
   pol.M = M;
   pol.Mw = Mw;
@@ -116,31 +116,49 @@ int gauss_radius(double sigma) {
   return (int)ceil(3.0 * sigma - 1e-12);
 }
 
+// The box sums accumulate in FP64 (LMR_ACC_F64) or in compensated FP32
+// (LMR_ACC_F32C); the image type picks the loads.
 hipError_t launch_fstat(const void* F, lmr_dtype t, const Geom& g, const lmr_params& p,
                         double* fstat, hipStream_t s) {
-  if (t == LMR_BF16) return fstat_t(static_cast<const uint16_t*>(F), g, p, fstat, s);
-  return fstat_t(static_cast<const float*>(F), g, p, fstat, s);
+  if (t == LMR_BF16) {
+    const uint16_t* f = static_cast<const uint16_t*>(F);
+    return p.accum == LMR_ACC_F32C ? fstat_t<uint16_t, F32C>(f, g, p, fstat, s)
+                                   : fstat_t<uint16_t, double>(f, g, p, fstat, s);
+  }
+  const float* f = static_cast<const float*>(F);
+  return p.accum == LMR_ACC_F32C ? fstat_t<float, F32C>(f, g, p, fstat, s)
+                                 : fstat_t<float, double>(f, g, p, fstat, s);
 }
 
 hipError_t launch_fwd(const void* F, lmr_dtype t, const float* Mw, const double* fstat,
                       const Geom& g, const lmr_params& p, const DevState* st, float* maps,
                       double* partials, float* cc_map, hipStream_t s) {
-  if (t == LMR_BF16)
-    return fwd_t(static_cast<const uint16_t*>(F), Mw, fstat, g, p, st, maps, partials,
-                 cc_map, s);
-  return fwd_t(static_cast<const float*>(F), Mw, fstat, g, p, st, maps, partials, cc_map,
-               s);
+  if (t == LMR_BF16) {
+    const uint16_t* f = static_cast<const uint16_t*>(F);
+    return p.accum == LMR_ACC_F32C
+               ? fwd_t<uint16_t, F32C>(f, Mw, fstat, g, p, st, maps, partials, cc_map, s)
+               : fwd_t<uint16_t, double>(f, Mw, fstat, g, p, st, maps, partials, cc_map, s);
+  }
+  const float* f = static_cast<const float*>(F);
+  return p.accum == LMR_ACC_F32C
+             ? fwd_t<float, F32C>(f, Mw, fstat, g, p, st, maps, partials, cc_map, s)
+             : fwd_t<float, double>(f, Mw, fstat, g, p, st, maps, partials, cc_map, s);
 }
 
 hipError_t launch_bwd(const void* F, const void* M, lmr_dtype t, const float* Mw,
                       const float* maps, const Geom& g, const lmr_params& p,
                       const DevState* st, const float* U0, const float* U1,
                       const float* ue, const float* dMw, float* graw, hipStream_t s) {
-  if (t == LMR_BF16)
-    return bwd_t(static_cast<const uint16_t*>(F), static_cast<const uint16_t*>(M), Mw,
-                 maps, g, p, st, U0, U1, ue, dMw, graw, s);
-  return bwd_t(static_cast<const float*>(F), static_cast<const float*>(M), Mw, maps, g,
-               p, st, U0, U1, ue, dMw, graw, s);
+  if (t == LMR_BF16) {
+    const uint16_t *f = static_cast<const uint16_t*>(F), *m = static_cast<const uint16_t*>(M);
+    return p.accum == LMR_ACC_F32C
+               ? bwd_t<uint16_t, F32C>(f, m, Mw, maps, g, p, st, U0, U1, ue, dMw, graw, s)
+               : bwd_t<uint16_t, double>(f, m, Mw, maps, g, p, st, U0, U1, ue, dMw, graw, s);
+  }
+  const float *f = static_cast<const float*>(F), *m = static_cast<const float*>(M);
+  return p.accum == LMR_ACC_F32C
+             ? bwd_t<float, F32C>(f, m, Mw, maps, g, p, st, U0, U1, ue, dMw, graw, s)
+             : bwd_t<float, double>(f, m, Mw, maps, g, p, st, U0, U1, ue, dMw, graw, s);
 }
 
 hipError_t launch_smooth(const float* graw, const Geom& g, const lmr_params& p,

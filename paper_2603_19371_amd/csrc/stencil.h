@@ -24,11 +24,51 @@
 // sums it with its taps.
 #pragma once
 
+#include <type_traits>
+
 #include "lmr_internal.h"
 
 namespace lmr {
 
 constexpr int kTX = 32;
+
+// Compensated FP32 accumulator (the LMR_ACC_F32C box sums): an unevaluated
+// sum hi + lo of two floats kept normalised (|lo| <= ulp(hi)/2).  Additions
+// use Knuth's TwoSum for the high parts and Dekker's FastTwoSum to
+// renormalise; a product of two floats enters exactly through the FMA
+// remainder.  With contraction off the sequences run as written.
+struct F32C {
+  float hi, lo;
+  F32C() = default;  // trivial, so LDS arrays may hold it; F32C() value-initialises to 0
+  __host__ __device__ explicit F32C(float v) : hi(v), lo(0.0f) {}
+  __device__ static F32C product(float a, float b) {
+    F32C r{};
+    r.hi = a * b;
+    r.lo = fmaf(a, b, -r.hi);
+    return r;
+  }
+  __device__ friend F32C operator+(const F32C& a, const F32C& b) {
+    const float s = a.hi + b.hi;
+    const float bb = s - a.hi;
+    float e = (a.hi - (s - bb)) + (b.hi - bb);
+    e += a.lo + b.lo;
+    F32C r{};
+    r.hi = s + e;
+    r.lo = e - (r.hi - s);
+    return r;
+  }
+  __device__ friend F32C operator-(const F32C& a, const F32C& b) {
+    F32C nb{};
+    nb.hi = -b.hi;
+    nb.lo = -b.lo;
+    return a + nb;
+  }
+  __device__ F32C& operator+=(const F32C& b) { return *this = *this + b; }
+};
+__device__ __forceinline__ double to_f64(double v) { return v; }
+__device__ __forceinline__ double to_f64(const F32C& v) {
+  return static_cast<double>(v.hi) + static_cast<double>(v.lo);
+}
 
 struct Tiling {
   int ty, tiles_x, tiles_y, nchunks, cz;
@@ -125,9 +165,9 @@ __device__ __forceinline__ void stencil_tile_in(
   A ring[W][NC], run[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    run[c] = A(0);
+    run[c] = A();
 #pragma unroll
-    for (int k = 0; k < W; ++k) ring[k][c] = A(0);
+    for (int k = 0; k < W; ++k) ring[k][c] = A();
   }
 
   const int zend = z1 + R;
@@ -144,7 +184,7 @@ __device__ __forceinline__ void stencil_tile_in(
           const int yy = i / LX, xx = i - yy * LX;
           A a[NC];
 #pragma unroll
-          for (int c = 0; c < NC; ++c) a[c] = A(0);
+          for (int c = 0; c < NC; ++c) a[c] = A();
 #pragma unroll
           for (int k = 0; k < W; ++k) {
             float r[NR];
@@ -158,13 +198,18 @@ __device__ __forceinline__ void stencil_tile_in(
         __syncthreads();
         A pl[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) pl[c] = A(0);
+        for (int c = 0; c < NC; ++c) pl[c] = A();
 #pragma unroll
         for (int k = 0; k < W; ++k)
 #pragma unroll
-          for (int c = 0; c < NC; ++c) pl[c] = fma(A(pol.wt(k)), s_y[c][ly][lx + k], pl[c]);
+          for (int c = 0; c < NC; ++c) {
+            if constexpr (P::kBox)
+              pl[c] += s_y[c][ly][lx + k];
+            else
+              pl[c] = fma(A(pol.wt(k)), s_y[c][ly][lx + k], pl[c]);
+          }
         A sm[NC];
-        if (P::kBox) {
+        if constexpr (P::kBox) {
           // ring[s] holds the plane that entered W steps ago
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
@@ -239,9 +284,9 @@ __device__ __forceinline__ void block_sum_to(double v, double* out) {
 // The window mean and variance of the fixed image do not change between
 // attempts: they are box-summed once per pair (at begin) and stored in FP64
 // as mu_F and sigma_FF, from sums of the exact products F^2.
-template <typename T>
+template <typename T, typename AccT = double>
 struct FStatPol {
-  using Acc = double;
+  using Acc = AccT;
   static constexpr int NRAW = 1, NCH = 2;
   static constexpr bool kBox = true, kSeparateLds = false;
   const T* __restrict__ F;
@@ -255,15 +300,20 @@ struct FStatPol {
   __device__ static constexpr double wt(int) { return 1.0; }
   __device__ Local begin_block(const DevState*) const { return Local{make_rbuf_n(F, N)}; }
   __device__ void load(const Local& l, unsigned i, float v[1]) const { v[0] = bld<T>(l.bF, i); }
-  __device__ void accum(double a[2], const float r[1], int) const {
-    const double f = r[0];
-    a[0] += f;
-    a[1] = fma(f, f, a[1]);
+  __device__ void accum(Acc a[2], const float r[1], int) const {
+    if constexpr (std::is_same<Acc, F32C>::value) {
+      a[0] += F32C(r[0]);
+      a[1] += F32C::product(r[0], r[0]);
+    } else {
+      const double f = r[0];
+      a[0] += f;
+      a[1] = fma(f, f, a[1]);
+    }
   }
-  __device__ void emit(Local&, int i, int, int, int, const double S[2]) const {
-    const double muF = S[0] * inv_n;
+  __device__ void emit(Local&, int i, int, int, int, const Acc S[2]) const {
+    const double muF = to_f64(S[0]) * inv_n;
     fstat[i] = muF;
-    fstat[N + i] = S[1] * inv_n - muF * muF;
+    fstat[N + i] = to_f64(S[1]) * inv_n - muF * muF;
   }
   __device__ void end_tile(Local&, int) const {}
 };
@@ -271,9 +321,9 @@ struct FStatPol {
 // ------------------------------------------------------------- forward (P2)
 // Box sums of Mw, Mw^2 and F Mw (exact products in FP64); mu_F and sigma_FF
 // come from FStatPol's pass over the same F.
-template <typename T, int NT>
+template <typename T, int NT, typename AccT = double>
 struct FwdPol {
-  using Acc = double;
+  using Acc = AccT;
   static constexpr int NRAW = 2, NCH = 3;
   static constexpr bool kBox = true, kSeparateLds = false;
   const T* __restrict__ F;
@@ -297,17 +347,23 @@ struct FwdPol {
     v[0] = bld<T>(l.bF, i);
     v[1] = bld<float>(l.bM, i);
   }
-  __device__ void accum(double a[3], const float r[2], int) const {
-    const double f = r[0], m = r[1];
-    a[0] += m;
-    a[1] = fma(m, m, a[1]);
-    a[2] = fma(f, m, a[2]);
+  __device__ void accum(Acc a[3], const float r[2], int) const {
+    if constexpr (std::is_same<Acc, F32C>::value) {
+      a[0] += F32C(r[1]);
+      a[1] += F32C::product(r[1], r[1]);
+      a[2] += F32C::product(r[0], r[1]);
+    } else {
+      const double f = r[0], m = r[1];
+      a[0] += m;
+      a[1] = fma(m, m, a[1]);
+      a[2] = fma(f, m, a[2]);
+    }
   }
-  __device__ void emit(Local& loc, int i, int, int, int, const double S[3]) const {
+  __device__ void emit(Local& loc, int i, int, int, int, const Acc S[3]) const {
     const double muF = fstat[i], sff = fstat[N + i];
-    const double muM = S[0] * inv_n;
-    const double sfm = S[2] * inv_n - muF * muM;
-    const double smm = S[1] * inv_n - muM * muM;
+    const double muM = to_f64(S[0]) * inv_n;
+    const double sfm = to_f64(S[2]) * inv_n - muF * muM;
+    const double smm = to_f64(S[1]) * inv_n - muM * muM;
     const double iD = 1.0 / (sff * smm + eps);
     const double c = sfm * sfm * iD;
     const double alpha = 2.0 * sfm * iD;
@@ -327,9 +383,9 @@ struct FwdPol {
 };
 
 // ------------------------------------------------------------ backward (P4)
-template <typename T>
+template <typename T, typename AccT = double>
 struct BwdPol {
-  using Acc = double;
+  using Acc = AccT;
   static constexpr int NRAW = 4, NCH = 4;
   static constexpr bool kBox = true, kSeparateLds = true;
   const T* __restrict__ F;
@@ -366,15 +422,20 @@ struct BwdPol {
 #pragma unroll
     for (int c = 0; c < 4; ++c) v[c] = bld<float>(l.bmap[c], i);
   }
-  __device__ void accum(double a[4], const float r[4], int) const {
+  __device__ void accum(Acc a[4], const float r[4], int) const {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) a[c] += static_cast<double>(r[c]);
+    for (int c = 0; c < 4; ++c) {
+      if constexpr (std::is_same<Acc, F32C>::value)
+        a[c] += F32C(r[c]);
+      else
+        a[c] += static_cast<double>(r[c]);
+    }
   }
-  __device__ void emit(const Local& loc, int i, int x, int y, int z,
-                       const double B[4]) const {
+  __device__ void emit(const Local& loc, int i, int x, int y, int z, const Acc Bs[4]) const {
     const int N = static_cast<int>(g.N);
     const float* u = loc.u;
     const double fj = ldf(F, i), mj = Mw[i];
+    const double B[4] = {to_f64(Bs[0]), to_f64(Bs[1]), to_f64(Bs[2]), to_f64(Bs[3])};
     const double dS = (fj * B[0] - B[1] + 2.0 * mj * B[2] - 2.0 * B[3]) * inv_n;
     const float d = static_cast<float>(dS);
     float gm[3];

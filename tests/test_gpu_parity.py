@@ -130,6 +130,30 @@ def test_loss_and_gradients_match_oracle(L, orc, window, sigma):
     assert e < 2e-5 * gmax, e
 
 
+@pytest.mark.parametrize("window,sigma", [(5, 0.7), (9, 1.6)])
+def test_compensated_fp32_sums_match_oracle(L, orc, window, sigma):
+    """Box sums kept as unevaluated FP32 pairs (LMR_ACC_F32C) carry about
+    twice FP32's significand, so loss and gradients meet the same bounds as
+    the FP64 sums."""
+    F, M = smooth_pair(RAGGED, 30 + window)
+    rng = np.random.default_rng(12)
+    u = (rng.uniform(-2, 2, (3,) + RAGGED)).astype(np.float32)
+    ctx = L.Context(RAGGED, window=window, grad_sigma=sigma, accum=1)
+    loss, gr, gs, cc = ctx.loss_grad(dev(F), dev(M), dev(u), cc=True)
+    rL, rg = orc.loss_grad(F, M, u, window, 1e-5)
+    rMw = orc.warp(M, u)
+    _, rcc = orc.lncc(F, rMw, window, 1e-5, with_map=True)
+    print(f"[loss f32c w={window}] gpu={loss:.12f} oracle={rL:.12f}", flush=True)
+    assert abs(loss - rL) < 2e-7
+    e = report("cc(f32c)", host(cc), rcc)
+    assert e < 2e-6, e
+    gmax = np.abs(rg).max()
+    e = report("g_raw(f32c)", host(gr), rg)
+    assert e < 2e-5 * gmax, e
+    e = report("g_smooth(f32c)", host(gs), orc.gauss(rg, sigma))
+    assert e < 2e-5 * gmax, e
+
+
 def test_identical_images_give_minus_one_and_zero_gradient(L):
     F, _ = smooth_pair((24, 24, 40), 12)
     u = np.zeros((3, 24, 24, 40), np.float32)
@@ -273,7 +297,24 @@ def test_one_attempt_field_within_1e4(L, orc):
     assert abs(st["loss"] - pr.state.loss) < 1e-6
 
 
-def _teacher_forced(L, orc, F_or, M_or, F_gpu, M_gpu, img_dtype, n, refs, window=5):
+def test_one_attempt_field_within_1e4_compensated_fp32(L, orc):
+    ph = _config1(0)
+    ctx = L.Context(ph.F.shape, window=5, accum=1)
+    ctx.begin(dev(ph.F), dev(ph.M), lambda0=1.0)
+    ctx.step_forced(dev(ph.F), dev(ph.M), [1])
+    pr, _, _ = _oracle_run(orc, ph.F, ph.M, 1, orc.Params(window=5), forces=[1])
+    e = report("field(1 attempt, f32c)", host(ctx.field()), pr.u)
+    assert e < 1e-4, e
+    assert abs(ctx.state()["loss"] - pr.state.loss) < 1e-6
+
+
+def test_batch_rejects_compensated_fp32(L):
+    with pytest.raises(L.LmrError):
+        L.Batch([(24, 24, 24)], window=5, accum=1)
+
+
+def _teacher_forced(L, orc, F_or, M_or, F_gpu, M_gpu, img_dtype, n, refs, window=5,
+                    accum=0):
     """Runs the oracle's own config-1 trajectory (automatic decisions) and, at
     every attempt t, restarts the GPU from the oracle's accepted state: the
     field rounded to FP32 (the library's storage), lambda and the loss
@@ -284,7 +325,7 @@ def _teacher_forced(L, orc, F_or, M_or, F_gpu, M_gpu, img_dtype, n, refs, window
     the worst candidate-loss error against the first reference."""
     p = orc.Params(window=window)
     traj = orc.Pair(F_or, M_or, p).begin(lambda0=1.0)
-    ctx = L.Context(F_or.shape, img_dtype=img_dtype, window=window)
+    ctx = L.Context(F_or.shape, img_dtype=img_dtype, window=window, accum=accum)
     errs = {name: [] for name, *_ in refs}
     worst_loss = 0.0
     for t in range(n):
@@ -339,6 +380,23 @@ def test_teacher_forced_bf16_images(L, orc):
                              ("fp32-images", ph.F, ph.M, 5e-3)])
     assert max(errs["bf16-images"]) < 1e-4
     assert errs["fp32-images"][0] < 5e-3
+
+
+def test_teacher_forced_bf16_images_compensated_fp32(L, orc):
+    """The precision form with compensated FP32 box sums in place of FP64
+    ones: BF16 images, FP32 field, FP64 loss reduction.  Every attempt
+    within 1e-4 of the oracle on the same BF16 values; the first within
+    5e-3 of the oracle on the FP32 images."""
+    from paper_2603_19371_amd.phantoms import bf16_to_f32, to_bf16_rne
+    ph = _config1(1)
+    Fr, Mr = bf16_to_f32(to_bf16_rne(ph.F)), bf16_to_f32(to_bf16_rne(ph.M))
+    errs, wl = _teacher_forced(
+        L, orc, ph.F, ph.M, dev(Fr, torch.bfloat16), dev(Mr, torch.bfloat16),
+        torch.bfloat16, 10, [("bf16-images f32c", Fr, Mr, 1e-4),
+                             ("fp32-images f32c", ph.F, ph.M, 5e-3)], accum=1)
+    assert max(errs["bf16-images f32c"]) < 1e-4
+    assert errs["fp32-images f32c"][0] < 5e-3
+    assert wl < 1e-6
 
 
 def test_lung_precision_form(L, orc):
