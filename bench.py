@@ -18,16 +18,20 @@ Printed on one JSON line, with
                 same workload (attempts at the full-resolution level).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--workload brain|lung|batch]
+                    [--workload brain|lung|abdomen|batch] [--accum f64|f32c]
 
-The default workload is the brain registration above.  Two more workloads
+The default workload is the brain registration above.  Three more workloads
 print a line of the same form:
-  lung   384^3 lung-CT-like pair with BF16 images (FP32 field, FP64 loss),
-         pyramid 2x/1x with 100/50 attempts;
-  batch  16 brain-like pairs of uneven shapes (4 x 96^3, 4 x 128x160x128,
-         4 x 160x192x224, 4 x 192x160x256) advanced together, one persistent
-         launch per attempt replayed from a HIP graph, tiling autotuned,
-         150 attempts at full resolution.
+  lung     384^3 lung-CT-like pair with BF16 images (FP32 field, FP64 loss),
+           pyramid 2x/1x with 100/50 attempts;
+  abdomen  192x160x192 abdomen-like cross-modal pair (CT-like fixed, MR-like
+           moving), FP32, the brain's pyramid and attempts;
+  batch    16 brain-like pairs of uneven shapes (4 x 96^3, 4 x 128x160x128,
+           4 x 160x192x224, 4 x 192x160x256) advanced together, one persistent
+           launch per attempt replayed from a HIP graph, tiling autotuned,
+           150 attempts at full resolution.
+--accum selects the LNCC box-sum accumulator: exact FP32 products summed in
+FP64 (default) or compensated FP32 pairs (the batched form takes f64 only).
 """
 from __future__ import annotations
 
@@ -45,6 +49,9 @@ FACTORS = (4, 2, 1)
 ITERS = (200, 100, 50)
 WINDOW, SIGMA = 7, 1.0
 HBM_PEAK_GBS = 8000.0
+# box-sum accumulator of the LNCC passes (lmr_params.accum)
+ACCUM = {"f64": 0, "f32c": 1}
+ACCUM_TEXT = {"f64": "FP64 box sums", "f32c": "compensated FP32 box sums"}
 
 # Algorithmic bytes per voxel that each kernel must move given its inputs and
 # outputs (each array read or written once; s = bytes per image voxel).
@@ -119,7 +126,8 @@ def _pyramid_line(a, F, M, img_dtype, factors, iters, workload, s):
     from paper_2603_19371_amd import _lib
 
     shape = tuple(F.shape)
-    pyr = _lib.Pyramid(shape, factors, img_dtype=img_dtype, window=WINDOW, grad_sigma=SIGMA)
+    pyr = _lib.Pyramid(shape, factors, img_dtype=img_dtype, window=WINDOW, grad_sigma=SIGMA,
+                       accum=ACCUM[a.accum])
     out = torch.empty((3,) + shape, device="cuda")
     for _ in range(a.warmup):
         pyr.run(F, M, iters, lambda0=1.0, out=out)
@@ -184,13 +192,13 @@ def run_brain(a):
     ph = phantoms.brain(SHAPE, seed=0)
     F = torch.from_numpy(ph.F).cuda()
     M = torch.from_numpy(ph.M).cuda()
-    workload = "brain160x192x224_f32_w7"
+    workload = "brain160x192x224_f32_w7" + ("" if a.accum == "f64" else "_f32c")
     value, elapsed, vox_att, roofline, detail = _pyramid_line(
         a, F, M, torch.float32, FACTORS, ITERS, workload, 4)
     cpu = None if a.no_cpu_baseline else cpu_baseline(ph.F, ph.M)
     config = {"workload": "brain-MRI-like phantom 160x192x224, FP32 images and field, "
-                          "LNCC w=7, sigma_g=1, pyramid 4x/2x/1x with 200/100/50 "
-                          "attempts, lambda0=1, x2/x0.5, tau=0",
+                          f"{ACCUM_TEXT[a.accum]}, LNCC w=7, sigma_g=1, pyramid 4x/2x/1x "
+                          "with 200/100/50 attempts, lambda0=1, x2/x0.5, tau=0",
               "pairs": 1, "voxel_attempts_per_step": vox_att}
     return "f32", value, elapsed, config, roofline, cpu, detail
 
@@ -205,7 +213,7 @@ def run_lung(a):
     bits = phantoms.to_bf16_rne(ph.F)
     F = torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16)
     M = torch.from_numpy(phantoms.to_bf16_rne(ph.M).view(np.int16)).cuda().view(torch.bfloat16)
-    workload = "lung384_bf16_w7"
+    workload = "lung384_bf16_w7" + ("" if a.accum == "f64" else "_f32c")
     factors, iters = (2, 1), (100, 50)
     value, elapsed, vox_att, roofline, detail = _pyramid_line(
         a, F, M, torch.bfloat16, factors, iters, workload, 2)
@@ -215,11 +223,33 @@ def run_lung(a):
         Fc = phantoms.bf16_to_f32(bits)[c].copy()
         Mc = phantoms.bf16_to_f32(phantoms.to_bf16_rne(ph.M))[c].copy()
         cpu = cpu_baseline(Fc, Mc, what="a centred 128^3 crop of the BF16 lung pair")
-    config = {"workload": "lung-CT-like phantom 384^3, BF16 images, FP32 field, FP64 "
-                          "loss reduction, LNCC w=7, sigma_g=1, pyramid 2x/1x with "
-                          "100/50 attempts, lambda0=1, x2/x0.5, tau=0",
+    config = {"workload": "lung-CT-like phantom 384^3, BF16 images, FP32 field, "
+                          f"{ACCUM_TEXT[a.accum]}, FP64 loss reduction, LNCC w=7, "
+                          "sigma_g=1, pyramid 2x/1x with 100/50 attempts, lambda0=1, "
+                          "x2/x0.5, tau=0",
               "pairs": 1, "voxel_attempts_per_step": vox_att}
     return "bf16", value, elapsed, config, roofline, cpu, detail
+
+
+def run_abdomen(a):
+    import torch
+    from paper_2603_19371_amd import phantoms
+
+    shape = (192, 160, 192)
+    ph = phantoms.abdomen(shape, seed=0)
+    F = torch.from_numpy(ph.F).cuda()
+    M = torch.from_numpy(ph.M).cuda()
+    workload = "abdomen192x160x192_f32_w7" + ("" if a.accum == "f64" else "_f32c")
+    value, elapsed, vox_att, roofline, detail = _pyramid_line(
+        a, F, M, torch.float32, FACTORS, ITERS, workload, 4)
+    cpu = None if a.no_cpu_baseline else cpu_baseline(
+        ph.F, ph.M, what="the full-resolution level of the abdomen pair")
+    config = {"workload": "abdomen-like cross-modal phantom 192x160x192 (CT-like fixed, "
+                          "MR-like moving), FP32 images and field, "
+                          f"{ACCUM_TEXT[a.accum]}, LNCC w=7, sigma_g=1, pyramid 4x/2x/1x "
+                          "with 200/100/50 attempts, lambda0=1, x2/x0.5, tau=0",
+              "pairs": 1, "voxel_attempts_per_step": vox_att}
+    return "f32", value, elapsed, config, roofline, cpu, detail
 
 
 BATCH_SHAPES = [(96, 96, 96)] * 4 + [(128, 160, 128)] * 4 + [(160, 192, 224)] * 4 + \
@@ -289,14 +319,22 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("brain", "lung", "batch"), default="brain")
+    ap.add_argument("--workload", choices=("brain", "lung", "abdomen", "batch"),
+                    default="brain")
+    ap.add_argument("--accum", choices=tuple(ACCUM), default="f64",
+                    help="box-sum accumulator of the LNCC passes (the batched form "
+                         "takes f64 only)")
     a = ap.parse_args()
+    if a.workload == "batch" and a.accum != "f64":
+        print("the batched form sums in FP64 only", file=sys.stderr)
+        sys.exit(2)
     if a.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(one pair's registration runs on one device).", file=sys.stderr)
         sys.exit(2)
 
-    run = {"brain": run_brain, "lung": run_lung, "batch": run_batch}[a.workload]
+    run = {"brain": run_brain, "lung": run_lung, "abdomen": run_abdomen,
+           "batch": run_batch}[a.workload]
     dtype, value, elapsed, config, roofline, cpu, detail = run(a)
     line = {
         "metric": "voxel-attempts/s of the LM step (full coarse-to-fine registration)"

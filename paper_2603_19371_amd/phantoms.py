@@ -229,6 +229,69 @@ def lung(shape=(384, 384, 384), seed=0, field_sigma=8.0, max_disp=6.0,
                    dict(kind="lung", seed=seed, shape=shape))
 
 
+# ------------------------------------------- abdomen, cross-modal (MR -> CT)
+# class intensities of the two modalities, normalised to [0, 1]:
+# background, fat, muscle and soft tissue, liver, spleen, kidney, bone
+ABDOMEN_CT = (0.0, 0.33, 0.52, 0.57, 0.55, 0.60, 0.92)
+ABDOMEN_MR = (0.0, 0.88, 0.30, 0.42, 0.62, 0.72, 0.12)
+
+
+def abdomen(shape=(192, 160, 192), seed=0, field_sigma=8.0, max_disp=6.0,
+            pv_sigma=0.7, noise=0.01, bias=0.15, texture=0.08):
+    """Abdomen-like cross-modal pair: one label map (an elliptical trunk with
+    a subcutaneous fat shell, liver, spleen, two kidneys and a vertebral
+    column, each ellipsoid jittered by the seed) rendered twice with
+    different class intensities, plus one smooth tissue texture common to
+    both.  The fixed image is the CT-like rendering;
+    the moving image is the MR-like rendering (a smooth multiplicative bias
+    field as well) warped by the inverse of the true field.  Axis 0 (z) runs
+    head to foot, axis 1 (y) front to back, axis 2 (x) right to left."""
+    rng = np.random.default_rng(seed)
+    shape = tuple(shape)
+    nz, ny, nx = shape
+    zz, yy, xx = _grid(shape)
+    zn, yn, xn = zz / nz - 0.5, yy / ny - 0.5, xx / nx - 0.5
+    del zz, yy, xx
+
+    def ell(c, a):
+        c = np.asarray(c) + rng.uniform(-0.02, 0.02, 3)
+        a = np.asarray(a) * rng.uniform(0.92, 1.08, 3)
+        return (((zn - c[0]) / a[0]) ** 2 + ((yn - c[1]) / a[1]) ** 2 +
+                ((xn - c[2]) / a[2]) ** 2) <= 1.0
+
+    lab = np.zeros(shape, np.uint8)
+    trunk = ((yn / 0.40) ** 2 + (xn / 0.46) ** 2) <= 1.0
+    inner = ((yn / 0.34) ** 2 + (xn / 0.40) ** 2) <= 1.0
+    lab[trunk] = 1
+    lab[inner] = 2
+    lab[ell((-0.12, -0.02, -0.18), (0.22, 0.20, 0.20)) & inner] = 3   # liver
+    lab[ell((-0.14, 0.08, 0.24), (0.12, 0.09, 0.08)) & inner] = 4    # spleen
+    for side in (-1, 1):                                               # kidneys
+        lab[ell((0.05, 0.18, side * 0.15), (0.10, 0.05, 0.05)) & inner] = 5
+    spine = (((yn - 0.24) / 0.06) ** 2 + (xn / 0.06) ** 2) <= 1.0
+    lab[spine & inner] = 6
+    del zn, yn, xn, trunk, inner, spine
+    coarse = 4 if min(shape) >= 64 else 1
+    # tissue texture: one smooth random pattern inside the body, shared by
+    # both renderings (it belongs to the anatomy, not to the modality)
+    tex = texture * _smooth_field(rng, shape, 2.0, 1.0, coarse=1)[0] * (lab > 0)
+    ct = ndi.gaussian_filter(np.array(ABDOMEN_CT)[lab] + tex, pv_sigma, mode="constant")
+    mr = ndi.gaussian_filter(np.array(ABDOMEN_MR)[lab] + tex, pv_sigma, mode="constant")
+    del tex
+    b = _smooth_field(rng, shape, 16.0, 1.0, coarse=coarse)[0]
+    mr = mr * (1.0 + bias * b)
+    del b
+    t = _smooth_field(rng, shape, field_sigma, max_disp, coarse=coarse)
+    w = invert_field(t, iters=30, coarse=coarse)
+    M0 = _resample(mr, w, order=1)
+    del w, mr
+    F = ct + noise * rng.standard_normal(shape)
+    M = M0 + noise * rng.standard_normal(shape)
+    return Phantom(F.astype(np.float32), M.astype(np.float32),
+                   t.astype(np.float32), lab,
+                   dict(kind="abdomen", seed=seed, shape=shape))
+
+
 # ------------------------------------------------------- uneven-size batch
 BATCH_SHAPES = ((96, 96, 96),) * 4 + ((128, 160, 128),) * 4 + \
                ((160, 192, 224),) * 4 + ((192, 160, 256),) * 4

@@ -308,6 +308,24 @@ def test_one_attempt_field_within_1e4_compensated_fp32(L, orc):
     assert abs(ctx.state()["loss"] - pr.state.loss) < 1e-6
 
 
+@pytest.mark.parametrize("accum", [0, 1])
+def test_abdomen_cross_modal_attempts_match_oracle(L, orc, accum):
+    """Abdomen-like cross-modal pair (CT-like fixed, MR-like moving), w = 7:
+    begin and three automatic attempts match the oracle within 1e-4 voxel,
+    with the same decisions."""
+    from paper_2603_19371_amd.phantoms import abdomen
+    ph = abdomen((48, 40, 48), seed=4)
+    ctx = L.Context(ph.F.shape, window=7, accum=accum)
+    ctx.begin(dev(ph.F), dev(ph.M), lambda0=1.0)
+    ctx.step(dev(ph.F), dev(ph.M), 3)
+    pr, dec, lams = _oracle_run(orc, ph.F, ph.M, 3, orc.Params(window=7))
+    st = ctx.state()
+    e = report(f"field(abdomen, 3 attempts, accum={accum})", host(ctx.field()), pr.u)
+    assert e < 1e-4, e
+    assert st["lambda_"] == lams[-1]
+    assert abs(st["loss"] - pr.state.loss) < 1e-6
+
+
 def test_batch_rejects_compensated_fp32(L):
     with pytest.raises(L.LmrError):
         L.Batch([(24, 24, 24)], window=5, accum=1)
