@@ -166,6 +166,50 @@ hipError_t launch_warp(const void* M, lmr_dtype t, const float* u, const Geom& g
   return hipGetLastError();
 }
 
+namespace {
+
+// compute units of the current device, cached per device (a tiling
+// heuristic only: 256 when the query fails)
+int device_cus() {
+  static int cus[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int n = 0;
+    const bool ok =
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess;
+    cus[dev] = ok && n > 0 ? n : 256;
+  }
+  return cus[dev];
+}
+
+// z-chunk of the staged form.  The blocks of a launch are co-resident and
+// each marches its chunk plane by plane, so a launch lasts about (most blocks
+// on one CU) x (planes per chunk + the two halo planes).  Among the chunk
+// counts that give chunks of at least 8 planes and at least 3/4 of
+// kStagedBlocks blocks, take the one that minimises that product (fewer
+// blocks on a tie).
+int staged_cz(int cols, int nz) {
+  const long long cus = device_cus();
+  int best_cz = 0;
+  long long best = 0;
+  for (int n = 1; n <= nz / 8; ++n) {
+    const int cz = (nz + n - 1) / n;
+    const long long blocks = (long long)cols * ((nz + cz - 1) / cz);
+    if (blocks < kStagedBlocks * 3 / 4) continue;
+    const long long cost = ((blocks + cus - 1) / cus) * (cz + 2);
+    if (best_cz == 0 || cost < best) {
+      best = cost;
+      best_cz = cz;
+    }
+  }
+  if (best_cz == 0)
+    best_cz = std::max(8, (int)(((long long)nz * cols + kStagedBlocks - 1) / kStagedBlocks));
+  return best_cz;
+}
+
+}  // namespace
+
 hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
                          const lmr_params& p, const DevState* st, const float* G,
                          float* U0, float* U1, const float* u_in, float* u_out,
@@ -178,8 +222,7 @@ hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
     // (small pyramid levels are latency-bound and keep one plane per block)
     const int cols = ((g.nx + kSX - 1) / kSX) * ((g.ny + kSY - 1) / kSY);
     if ((long long)cols * (g.nz / 8) >= kStagedMinBlocks) {
-      int cz = (int)(((long long)g.nz * cols + kStagedBlocks - 1) / kStagedBlocks);
-      cz = std::max(cz, 8);
+      const int cz = staged_cz(cols, g.nz);
       const dim3 sgrid(cols * ((g.nz + cz - 1) / cz));
       if (t == LMR_BF16)
         hipLaunchKernelGGL(k_update_staged<uint16_t>, sgrid, dim3(kSNT), 0, s,
