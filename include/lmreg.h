@@ -65,7 +65,8 @@ typedef enum { LMR_F32 = 0, LMR_BF16 = 1 } lmr_dtype;
  * gfx950 an FP64 add issues at the rate of an unpacked FP32 add).
  * LMR_ACC_F32C: compensated FP32, sums kept as normalised hi/lo float pairs
  * with TwoSum additions and exact FMA products; the window statistics are then
- * formed in FP64 from hi + lo.  The batched form takes LMR_ACC_F64 only. */
+ * formed in FP64 from hi + lo.  Both are available to every entry point,
+ * the batched form included. */
 typedef enum { LMR_ACC_F64 = 0, LMR_ACC_F32C = 1 } lmr_accum;
 
 /* Hyper-parameters of one registration.  The paper's own setting

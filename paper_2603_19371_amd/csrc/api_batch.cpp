@@ -93,8 +93,8 @@ lmr_status enqueue_steps(lmr_batch* b, int n) {
 
 std::string cache_key(const lmr_batch* b) {
   char buf[128];
-  snprintf(buf, sizeof buf, "gfx950|img%d|w%d|s%.3f|", (int)b->img, b->p.window,
-           b->p.grad_sigma);
+  snprintf(buf, sizeof buf, "gfx950|img%d|acc%d|w%d|s%.3f|", (int)b->img, b->p.accum,
+           b->p.window, b->p.grad_sigma);
   std::string k = buf;
   for (const auto& P : b->host) {
     snprintf(buf, sizeof buf, "%dx%dx%d,", P.g.nz, P.g.ny, P.g.nx);
@@ -124,9 +124,8 @@ lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes, lmr_
   if (!out || npairs < 1 || npairs > 4096 || !shapes) return LMR_EINVAL;
   *out = nullptr;
   if (!params_ok(p) || (img != LMR_F32 && img != LMR_BF16)) return LMR_EINVAL;
-  if (p->accum != LMR_ACC_F64) return LMR_EINVAL;  // the persistent kernel sums in FP64
   const int rb = p->window / 2, rg = gauss_r(p->grad_sigma);
-  const void* kernel = batch_kernel(img, rb, rg);
+  const void* kernel = batch_kernel(img, static_cast<lmr_accum>(p->accum), rb, rg);
   if (!kernel) return LMR_EINVAL;  // Gaussian radius beyond the instantiated range
   lmr_batch* b = new (std::nothrow) lmr_batch();
   if (!b) return LMR_ENOMEM;

@@ -1,241 +1,18 @@
-// Batched form: every pair of a batch of uneven-size pairs advances by one
-// LM attempt in ONE persistent launch.  The grid holds only as many blocks as
-// fit on the GPU at once (occupancy query); the blocks sweep the work list of
-// each phase and meet at a grid barrier between phases:
-//
-//   P1 update     work items: 256 consecutive voxels of a pair
-//   P2 lncc_fwd   work items: stencil tiles of a pair (partial of cc per tile)
-//   P3 decide     work items: pairs (one block reduces a pair's partials)
-//   P4 lncc_bwd   stencil tiles of the pairs whose candidate was accepted
-//   P5 smooth     stencil tiles of the pairs whose candidate was accepted
-//
-// Each pair keeps its own device state (lambda, loss history, decision), so
-// pairs accept, reject and freeze independently.  A barrier wait is bounded
-// in time: past the limit the kernel records an error and every block leaves
-// (later launches return at once), so a residency mistake cannot hang the
-// device.
-#include "decide.h"
-#include "lmr_batch.h"
-#include "stencil.h"
-#include "update.h"
+// Batched persistent form, FP64 box sums; the accumulator dispatch and the
+// launch of either instantiation set.
+#include "batch_attempt.h"
 
 namespace lmr {
 
-namespace {
-
-constexpr int kTY = 8;
-constexpr int kNT = kTX * kTY;
-static_assert(kBatchUpdateTX == kSX && kBatchUpdateTY == kSY && kNT == kSNT,
-              "update work items are staged-update tiles of one block");
-
-// Grid-wide barrier among `nblocks` co-resident blocks (two-level arrival on
-// monotonic counters, see BatchCtl).  A wait longer than `timeout` ticks of
-// the device's constant-rate wall clock records an error.  Returns false when
-// this wait timed out or another block reported one.
-__device__ bool grid_sync(BatchCtl* ctl, unsigned nblocks, unsigned long long timeout) {
-  __shared__ int ok;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    // release: this block's results are written back to where blocks on the
-    // other chiplets read them, before its arrival is counted
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned grp = blockIdx.x % kBarGroups;
-    const unsigned long long in_grp = (nblocks + kBarGroups - 1 - grp) / kBarGroups;
-    const unsigned long long ngrp = nblocks < (unsigned)kBarGroups ? nblocks : kBarGroups;
-    const unsigned long long a = atomicAdd(&ctl->group[grp].v, 1ull);
-    const unsigned long long epoch = a / in_grp;  // barriers completed before this one
-    bool release = false;
-    if ((a + 1) % in_grp == 0) {
-      const unsigned long long t = atomicAdd(&ctl->top.v, 1ull);
-      if ((t + 1) % ngrp == 0) {
-        __hip_atomic_fetch_add(&ctl->gen.v, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        release = true;
-      }
-    }
-    int good = 1;
-    if (!release) {
-      const unsigned long long t0 = wall_clock64();
-      // relaxed polls (an acquire per poll would invalidate this chiplet's L2
-      // under the working blocks every time); the fence below acquires once
-      while (__hip_atomic_load(&ctl->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <=
-             epoch) {
-        if (wall_clock64() - t0 > timeout ||
-            __hip_atomic_load(&ctl->error.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          good = 0;
-          atomicExch(&ctl->error.v, 1ull);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(4);
-      }
-    }
-    // acquire: stale lines of this chiplet's caches are dropped, so the
-    // results of the other blocks are read from memory
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    ok = good && __hip_atomic_load(&ctl->error.v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT) == 0;
-  }
-  __syncthreads();
-  return ok != 0;
-}
-
-// A state field written earlier in this launch by another block: read with a
-// device-scope atomic so that no cached copy is used.
-__device__ __forceinline__ int fresh(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// pair owning work item `it` of a list whose per-pair offsets are first[p]
-__device__ __forceinline__ int owner(const BatchPair* __restrict__ pairs, int npairs,
-                                     int it, bool tiles) {
-  int p = 0;
-  for (int k = 1; k < npairs; ++k)
-    if ((tiles ? pairs[k].tile0 : pairs[k].utile0) <= it) p = k;
-  return p;
-}
-
-template <int RB, int RG, typename T>
-__global__ void __launch_bounds__(kNT)
-    k_batch_attempt(const BatchPair* __restrict__ pairs, int npairs, int n_update_items,
-                    int n_tiles, BatchCtl* ctl, DecideParams dp,
-                    unsigned long long timeout) {
-  const int nb = gridDim.x;
-  // the phases are separated by grid barriers, so their LDS is overlaid
-  __shared__ union {
-    StagedLds upd;
-    StencilLds<RB, kTY, FwdPol<T, kNT>> fwd;
-    StencilLds<RB, kTY, BwdPol<T>> bwd;
-    StencilLds<RG, kTY, SmoothPol<RG>> smo;
-  } lds;
-  // after a barrier timeout every later launch returns at once
-  if (__hip_atomic_load(&ctl->error.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-
-  // P1: closed form, compositive integration, candidate warp (and its
-  // derivative, which P4 reads), one staged tile per work item
-  for (int it = blockIdx.x; it < n_update_items; it += nb) {
-    const BatchPair& P = pairs[owner(pairs, npairs, it, false)];
-    if (P.st->stalled) continue;
-    UpdateArgs a = update_args_from_state(P.st, P.U0, P.U1, P.G, P.Mw, P.eps, P.compositive);
-    a.dMw = P.graw;
-    const int local = it - P.utile0;
-    const int tx = (P.g.nx + kSX - 1) / kSX, ty = (P.g.ny + kSY - 1) / kSY;
-    const int bx = (local % tx) * kSX, by = ((local / tx) % ty) * kSY;
-    const int z0 = (local / (tx * ty)) * P.ucz;
-    const int z1 = min(z0 + P.ucz, P.g.nz);
-    if (P.compositive) {
-      staged_update_tile(static_cast<const T*>(P.M), P.g, a, bx, by, z0, z1, lds.upd);
-    } else {
-      const int x = bx + static_cast<int>(threadIdx.x) % kSX;
-      const int y = by + static_cast<int>(threadIdx.x) / kSX;
-      if (x < P.g.nx && y < P.g.ny)
-        for (int z = z0; z < z1; ++z) update_voxel(static_cast<const T*>(P.M), P.g, a, x, y, z);
-    }
-  }
-  if (!grid_sync(ctl, nb, timeout)) return;
-
-  // P2: LNCC forward, one partial of cc per tile
-  for (int it = blockIdx.x; it < n_tiles; it += nb) {
-    const BatchPair& P = pairs[owner(pairs, npairs, it, true)];
-    if (P.st->stalled) continue;
-    FwdPol<T, kNT> pol;
-    pol.F = static_cast<const T*>(P.F);
-    pol.Mw = P.Mw;
-    pol.fstat = P.fstat;
-    pol.maps = P.maps;
-    pol.cc = nullptr;
-    pol.partials = P.partials;
-    pol.N = static_cast<int>(P.g.N);
-    pol.inv_n = P.inv_n;
-    pol.eps = P.cc_eps;
-    const int local = it - P.tile0;
-    int x0, y0, z0;
-    tile_origin(P.t, local, kTY, x0, y0, z0);
-    auto loc = pol.begin_block(P.st);
-    stencil_tile<RB, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc, lds.fwd);
-    pol.end_tile(loc, local);
-  }
-  if (!grid_sync(ctl, nb, timeout)) return;
-
-  // P3: per-pair FP64 reduction and decision
-  for (int p = blockIdx.x; p < npairs; p += nb) {
-    const BatchPair& P = pairs[p];
-    decide_block<kNT>(P.st, P.partials, P.t.tiles(), P.g.N, dp, 0, -1, 0.0, nullptr);
-  }
-  if (!grid_sync(ctl, nb, timeout)) return;
-
-  // P4: LNCC and warp backward of the accepted candidates
-  for (int it = blockIdx.x; it < n_tiles; it += nb) {
-    const BatchPair& P = pairs[owner(pairs, npairs, it, true)];
-    if (fresh(&P.st->stalled) || !fresh(&P.st->accepted)) continue;
-    BwdPol<T> pol;
-    pol.F = static_cast<const T*>(P.F);
-    pol.M = static_cast<const T*>(P.M);
-    pol.Mw = P.Mw;
-    pol.maps = P.maps;
-    pol.U0 = P.U0;
-    pol.U1 = P.U1;
-    pol.u_explicit = fresh(&P.st->cur) ? P.U1 : P.U0;  // the accepted candidate
-    pol.dMw = P.graw;  // stored there by P1 for the candidate
-    pol.graw = P.graw;
-    pol.g = P.g;
-    pol.inv_n = P.inv_n;
-    int x0, y0, z0;
-    tile_origin(P.t, it - P.tile0, kTY, x0, y0, z0);
-    auto loc = pol.begin_block(nullptr);
-    stencil_tile<RB, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc, lds.bwd);
-  }
-  if (!grid_sync(ctl, nb, timeout)) return;
-
-  // P5: Gaussian smoothing of the new gradient
-  for (int it = blockIdx.x; it < n_tiles; it += nb) {
-    const BatchPair& P = pairs[owner(pairs, npairs, it, true)];
-    if (fresh(&P.st->stalled) || !fresh(&P.st->accepted)) continue;
-    SmoothPol<RG> pol;
-    pol.in = P.graw;
-    pol.out = P.G;
-    pol.N = static_cast<int>(P.g.N);
-#pragma unroll
-    for (int k = 0; k <= 2 * RG; ++k) pol.w[k] = P.gw[k];
-    int x0, y0, z0;
-    tile_origin(P.t, it - P.tile0, kTY, x0, y0, z0);
-    auto loc = pol.begin_block(P.st);
-    stencil_tile<RG, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc, lds.smo);
-  }
-}
-
-template <int RB, int RG, typename T>
-const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&k_batch_attempt<RB, RG, T>);
-}
-
-template <typename T>
-const void* kernel_for(int rb, int rg) {
-#define LMR_RG(RBV)                                \
-  switch (rg) {                                    \
-    case 0: return kernel_ptr<RBV, 0, T>();        \
-    case 1: return kernel_ptr<RBV, 1, T>();        \
-    case 2: return kernel_ptr<RBV, 2, T>();        \
-    case 3: return kernel_ptr<RBV, 3, T>();        \
-    case 4: return kernel_ptr<RBV, 4, T>();        \
-    default: return nullptr;                       \
-  }
-  switch (rb) {
-    case 1: LMR_RG(1)
-    case 2: LMR_RG(2)
-    case 3: LMR_RG(3)
-    case 4: LMR_RG(4)
-    default: return nullptr;
-  }
-#undef LMR_RG
-}
-
-}  // namespace
+const void* batch_kernel_f32c(lmr_dtype t, int box_radius, int gauss_radius);
 
 int batch_tile_rows() { return kTY; }
 int batch_block_threads() { return kNT; }
 
-const void* batch_kernel(lmr_dtype t, int box_radius, int gauss_radius) {
-  return t == LMR_BF16 ? kernel_for<uint16_t>(box_radius, gauss_radius)
-                       : kernel_for<float>(box_radius, gauss_radius);
+const void* batch_kernel(lmr_dtype t, lmr_accum accum, int box_radius, int gauss_radius) {
+  if (accum == LMR_ACC_F32C) return batch_kernel_f32c(t, box_radius, gauss_radius);
+  if (accum != LMR_ACC_F64) return nullptr;
+  return batch_kernel_for<double>(t, box_radius, gauss_radius);
 }
 
 hipError_t launch_batch_attempt(const void* kernel, int grid, const BatchPair* pairs,

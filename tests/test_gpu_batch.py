@@ -34,17 +34,19 @@ def host(t):
     return t.cpu().numpy()
 
 
-def test_batch_matches_per_pair_runs(L, pairs):
+@pytest.mark.parametrize("accum", [0, 1])
+def test_batch_matches_per_pair_runs(L, pairs, accum):
     """Every pair of the batch follows exactly (bitwise) the run of a
-    stand-alone context: same kernels, same tiling, same reduction order."""
+    stand-alone context: same kernels, same tiling, same reduction order;
+    with either box-sum accumulator."""
     n = 6
     ref = []
     for (F, M), sh in zip(pairs, SHAPES):
-        c = L.Context(sh, window=5)
+        c = L.Context(sh, window=5, accum=accum)
         c.begin(F, M)
         c.step(F, M, n)
         ref.append((host(c.field()), c.state()))
-    b = L.Batch(SHAPES, window=5)
+    b = L.Batch(SHAPES, window=5, accum=accum)
     b.begin([F for F, _ in pairs], [M for _, M in pairs])
     b.step(n, graph=True)
     b.sync()

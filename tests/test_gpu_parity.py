@@ -326,11 +326,6 @@ def test_abdomen_cross_modal_attempts_match_oracle(L, orc, accum):
     assert abs(st["loss"] - pr.state.loss) < 1e-6
 
 
-def test_batch_rejects_compensated_fp32(L):
-    with pytest.raises(L.LmrError):
-        L.Batch([(24, 24, 24)], window=5, accum=1)
-
-
 def _teacher_forced(L, orc, F_or, M_or, F_gpu, M_gpu, img_dtype, n, refs, window=5,
                     accum=0):
     """Runs the oracle's own config-1 trajectory (automatic decisions) and, at
