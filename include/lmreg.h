@@ -63,8 +63,9 @@ typedef enum { LMR_F32 = 0, LMR_BF16 = 1 } lmr_dtype;
 /* Accumulator of the LNCC box sums (forward, backward and the fixed image's
  * statistics).  LMR_ACC_F64: exact FP32 products summed in FP64 (default: on
  * gfx950 an FP64 add issues at the rate of an unpacked FP32 add).
- * LMR_ACC_F32C: compensated FP32, sums kept as normalised hi/lo float pairs
- * with TwoSum additions and exact FMA products; the window statistics are then
+ * LMR_ACC_F32C: compensated FP32, sums kept as hi/lo float pairs by cascaded
+ * summation (TwoSum on the high parts, the rounding errors collected in the
+ * low parts) with exact FMA products; the window statistics are then
  * formed in FP64 from hi + lo.  Both are available to every entry point,
  * the batched form included. */
 typedef enum { LMR_ACC_F64 = 0, LMR_ACC_F32C = 1 } lmr_accum;

@@ -33,10 +33,13 @@ namespace lmr {
 constexpr int kTX = 32;
 
 // Compensated FP32 accumulator (the LMR_ACC_F32C box sums): an unevaluated
-// sum hi + lo of two floats kept normalised (|lo| <= ulp(hi)/2).  Additions
-// use Knuth's TwoSum for the high parts and Dekker's FastTwoSum to
-// renormalise; a product of two floats enters exactly through the FMA
-// remainder.  With contraction off the sequences run as written.
+// sum hi + lo of two floats, accumulated by cascaded summation.  The high
+// parts add with Knuth's TwoSum, whose exact rounding error joins the low
+// parts, which add plainly; a product of two floats enters exactly through
+// the FMA remainder.  No renormalisation between additions: a box sum takes
+// at most a few dozen of them, so lo stays a few ulps of hi and hi + lo
+// carries about twice FP32's significand.  With contraction off the
+// sequences run as written.
 struct F32C {
   float hi, lo;
   F32C() = default;  // trivial, so LDS arrays may hold it; F32C() value-initialises to 0
@@ -48,13 +51,11 @@ struct F32C {
     return r;
   }
   __device__ friend F32C operator+(const F32C& a, const F32C& b) {
-    const float s = a.hi + b.hi;
-    const float bb = s - a.hi;
-    float e = (a.hi - (s - bb)) + (b.hi - bb);
-    e += a.lo + b.lo;
     F32C r{};
-    r.hi = s + e;
-    r.lo = e - (r.hi - s);
+    r.hi = a.hi + b.hi;
+    const float bb = r.hi - a.hi;
+    const float e = (a.hi - (r.hi - bb)) + (b.hi - bb);
+    r.lo = (a.lo + b.lo) + e;
     return r;
   }
   __device__ friend F32C operator-(const F32C& a, const F32C& b) {
