@@ -10,9 +10,24 @@ namespace {
 
 constexpr int kTY = 8;
 
+// Waves per SIMD a stencil instantiation must leave register room for.
+// The forward pass on BF16 images with compensated FP32 sums needs 130
+// VGPRs left alone, two above the 128 that allow four waves; asked for four,
+// the compiler fits it in 128 without spilling.  The others keep the
+// compiler's own choice.
+template <class P>
+struct StencilWaves {
+  static constexpr int value = 1;
+};
+template <int NT>
+struct StencilWaves<FwdPol<uint16_t, NT, F32C>> {
+  static constexpr int value = 4;
+};
+
 // need: 0 always run, 1 skip a frozen pair, 2 run only after an acceptance
 template <int R, int TY, class P>
 __global__ void __launch_bounds__(kTX* TY)
+    __attribute__((amdgpu_waves_per_eu(StencilWaves<P>::value)))
     k_stencil(const P pol, Geom g, Tiling t, const DevState* st, int need) {
   if (st && need) {
     if (st->stalled) return;
