@@ -4,8 +4,6 @@
 
 namespace lmr {
 
-const void* batch_kernel_f32c(lmr_dtype t, int box_radius, int gauss_radius);
-
 int batch_tile_rows() { return kTY; }
 int batch_block_threads() { return kNT; }
 

@@ -62,6 +62,8 @@ int batch_block_threads();
 // 1..4, Gaussian radius 0..4), or null when that combination is not
 // instantiated.
 const void* batch_kernel(lmr_dtype t, lmr_accum accum, int box_radius, int gauss_radius);
+// the compensated-FP32 set of the above (k_batch_f32c.hip)
+const void* batch_kernel_f32c(lmr_dtype t, int box_radius, int gauss_radius);
 hipError_t launch_batch_attempt(const void* kernel, int grid, const BatchPair* pairs,
                                 int npairs, int n_update_items, int n_tiles, BatchCtl* ctl,
                                 const DecideParams& dp, unsigned long long timeout,
