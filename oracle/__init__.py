@@ -40,7 +40,12 @@ class _Params(C.Structure):
                 ("compositive", C.c_int), ("lambda_inc", C.c_double),
                 ("lambda_dec", C.c_double), ("lambda_min", C.c_double),
                 ("lambda_max", C.c_double), ("tau", C.c_double),
-                ("max_retries", C.c_int)]
+                ("max_retries", C.c_int), ("tile", C.c_int)]
+
+
+class _Adam(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double)]
 
 
 class _State(C.Structure):
@@ -79,6 +84,11 @@ def lib():
             "orc_closed_form": (None, [_D, i, i, i, d, d, _D]),
             "orc_explicit_solve": (None, [_D, d, d, _D]),
             "orc_integrate": (None, [_D, _D, i, i, i, d, i, _D]),
+            "orc_tile_hessian": (None, [_D, i, i, i, i, _D]),
+            "orc_tile_step": (None, [_D, i, i, i, i, d, d, _D]),
+            "orc_adam_direction": (None, [_D, _D, _D, l, l, C.POINTER(_Adam), _D]),
+            "orc_adam_iter": (None, [C.POINTER(_Params), C.POINTER(_Adam), _D, _D, _D,
+                                     _D, _D, _D, i, i, i, l, C.POINTER(_State)]),
             "orc_decide": (i, [C.POINTER(_Params), C.POINTER(_State), d, i]),
             "orc_begin": (None, [C.POINTER(_Params), _D, _D, _D, i, i, i, d,
                                  C.POINTER(_State), _D]),
@@ -128,12 +138,25 @@ class Params:
     lambda_max: float = 1e6
     tau: float = 0.0
     max_retries: int = 10
+    tile: int = 1
 
     def c(self) -> _Params:
         return _Params(self.window, self.grad_sigma, self.cc_eps, self.step_eps,
                        self.compositive, self.lambda_inc, self.lambda_dec,
                        self.lambda_min, self.lambda_max, self.tau,
-                       self.max_retries)
+                       self.max_retries, self.tile)
+
+
+@dataclass
+class AdamParams:
+    """The Adam comparator's hyper-parameters (beta1, beta2 as in Sec. 3)."""
+    lr: float = 0.1
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+
+    def c(self) -> _Adam:
+        return _Adam(self.lr, self.beta1, self.beta2, self.eps)
 
 
 @dataclass
@@ -267,6 +290,35 @@ def explicit_solve(g, r, lam):
     return d
 
 
+def tile_hessian(gs, k):
+    """Pooled Hessian of tile side k (eq. tilen): [tz][ty][tx][6] with entries
+    (xx, yy, zz, xy, xz, yz), the mean of gs gs^T over each tile."""
+    gs = _f64(gs)
+    nz, ny, nx = gs.shape[1:]
+    t = tuple((n + k - 1) // k for n in (nz, ny, nx))
+    H = np.empty(t + (6,))
+    lib().orc_tile_hessian(_p(gs), nz, ny, nx, int(k), _p(H))
+    return H
+
+
+def tile_step(gs, k, r, lam):
+    gs = _f64(gs)
+    out = np.empty_like(gs)
+    lib().orc_tile_step(_p(gs), *gs.shape[1:], int(k), float(r), float(lam), _p(out))
+    return out
+
+
+def adam_direction(gs, m, v, t, ap: AdamParams):
+    """One bias-corrected Adam direction at step t; m and v (float64,
+    C-contiguous) are updated in place."""
+    gs = _f64(gs)
+    assert m.dtype == np.float64 and v.dtype == np.float64
+    du = np.empty_like(gs)
+    a = ap.c()
+    lib().orc_adam_direction(_p(gs), _p(m), _p(v), gs.size, int(t), C.byref(a), _p(du))
+    return du
+
+
 def integrate(u, v, eps=1.0, compositive=1):
     u, v = _f64(u), _f64(v)
     out = np.empty_like(u)
@@ -310,6 +362,40 @@ class Pair:
                                 int(force))
         self.state = State.from_c(cs)
         return bool(acc)
+
+
+@dataclass
+class AdamPair:
+    """The Adam comparator on one image pair: same loss, gradient, smoothing
+    and integration as the LM pair; the step comes from Adam's moments of
+    the smoothed gradient and is always kept."""
+    F: np.ndarray
+    M: np.ndarray
+    params: Params
+    adam: AdamParams = field(default_factory=AdamParams)
+    u: np.ndarray = None
+    gs: np.ndarray = None
+    m: np.ndarray = None
+    v: np.ndarray = None
+    t: int = 0
+    state: State = field(default_factory=State)
+
+    def begin(self, u0=None):
+        pr = Pair(self.F, self.M, self.params).begin(u0, lambda0=1.0)
+        self.F, self.M, self.u, self.gs, self.state = pr.F, pr.M, pr.u, pr.gs, pr.state
+        self.m = np.zeros_like(self.u)
+        self.v = np.zeros_like(self.u)
+        self.t = 0
+        return self
+
+    def iterate(self):
+        self.t += 1
+        cp, ca, cs = self.params.c(), self.adam.c(), self.state.c()
+        lib().orc_adam_iter(C.byref(cp), C.byref(ca), _p(self.F), _p(self.M), _p(self.u),
+                            _p(self.gs), _p(self.m), _p(self.v), *self.F.shape, self.t,
+                            C.byref(cs))
+        self.state = State.from_c(cs)
+        return self.state.loss
 
 
 # ---------------------------------------------------------------- O8, O9

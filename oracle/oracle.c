@@ -472,6 +472,108 @@ void orc_explicit_solve(const double g[3], double r, double lambda,
 }
 
 /* ------------------------------------------------------------------------ */
+/* O5' Pooled Hessian over tiles of side k (Sec. 2.2, eq. tilen; Sec. 3.2).  */
+/*   Readings: the tiles are the disjoint k^3 blocks of the grid from the    */
+/*   origin (the ablation sweeps even sides too, so not a centred window);   */
+/*   a block cut by a far face keeps its voxels inside the volume; the       */
+/*   pooled matrix is the mean of the voxels' rank-1 products, so that k = 1 */
+/*   is eq. tile1 and lambda keeps its scale for every k; each voxel solves  */
+/*   with its own smoothed gradient on the right-hand side.                  */
+/* ------------------------------------------------------------------------ */
+
+void orc_tile_hessian(const double* gs, int nz, int ny, int nx, int k, double* H) {
+  long N = (long)nz * ny * nx;
+  int tx = (nx + k - 1) / k, ty = (ny + k - 1) / k, tz = (nz + k - 1) / k;
+  for (int bz = 0; bz < tz; bz++)
+    for (int by = 0; by < ty; by++)
+      for (int bx = 0; bx < tx; bx++) {
+        double h[6] = {0, 0, 0, 0, 0, 0};
+        long cnt = 0;
+        for (int z = bz * k; z < bz * k + k && z < nz; z++)
+          for (int y = by * k; y < by * k + k && y < ny; y++)
+            for (int x = bx * k; x < bx * k + k && x < nx; x++) {
+              long i = IDX(z, y, x);
+              double a = gs[i], b = gs[N + i], c = gs[2 * N + i];
+              h[0] += a * a;
+              h[1] += b * b;
+              h[2] += c * c;
+              h[3] += a * b;
+              h[4] += a * c;
+              h[5] += b * c;
+              cnt++;
+            }
+        double* o = H + 6 * (((long)bz * ty + by) * tx + bx);
+        for (int e = 0; e < 6; e++) o[e] = h[e] / (double)cnt;
+      }
+}
+
+/* Gaussian elimination with partial pivoting of A d = b (3x3). */
+static void solve3(double A[3][4], double d[3]) {
+  for (int k = 0; k < 3; k++) {
+    int p = k;
+    for (int i = k + 1; i < 3; i++)
+      if (fabs(A[i][k]) > fabs(A[p][k])) p = i;
+    if (p != k)
+      for (int j = 0; j < 4; j++) {
+        double t = A[k][j];
+        A[k][j] = A[p][j];
+        A[p][j] = t;
+      }
+    for (int i = k + 1; i < 3; i++) {
+      double f = A[i][k] / A[k][k];
+      for (int j = k; j < 4; j++) A[i][j] -= f * A[k][j];
+    }
+  }
+  for (int i = 2; i >= 0; i--) {
+    double s = A[i][3];
+    for (int j = i + 1; j < 3; j++) s -= A[i][j] * d[j];
+    d[i] = s / A[i][i];
+  }
+}
+
+void orc_tile_step(const double* gs, int nz, int ny, int nx, int k, double r,
+                   double lambda, double* du) {
+  long N = (long)nz * ny * nx;
+  int tx = (nx + k - 1) / k, ty = (ny + k - 1) / k, tz = (nz + k - 1) / k;
+  double* H = (double*)malloc(sizeof(double) * 6 * (size_t)tx * ty * tz);
+  orc_tile_hessian(gs, nz, ny, nx, k, H);
+  for (int z = 0; z < nz; z++)
+    for (int y = 0; y < ny; y++)
+      for (int x = 0; x < nx; x++) {
+        long i = IDX(z, y, x);
+        const double* h = H + 6 * (((long)(z / k) * ty + y / k) * tx + x / k);
+        double A[3][4] = {{h[0] + lambda, h[3], h[4], -r * gs[i]},
+                          {h[3], h[1] + lambda, h[5], -r * gs[N + i]},
+                          {h[4], h[5], h[2] + lambda, -r * gs[2 * N + i]}};
+        double d[3];
+        solve3(A, d);
+        du[i] = d[0];
+        du[N + i] = d[1];
+        du[2 * N + i] = d[2];
+      }
+  free(H);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adam comparator (the paper's baseline, Sec. 3 and Sec. 3.5).  Readings:   */
+/*   the moments are taken of the smoothed gradient (the gradient the LM    */
+/*   step uses: Eulerian descent smooths the gradient before the optimizer  */
+/*   acts on it); the bias-corrected step -lr mhat / (sqrt(vhat) + eps) is  */
+/*   integrated by eq. compositive like the LM step; every step is kept.    */
+/* ------------------------------------------------------------------------ */
+
+void orc_adam_direction(const double* gs, double* m, double* v, long n, long t,
+                        const orc_adam_params* a, double* du) {
+  double c1 = 1.0 - pow(a->beta1, (double)t), c2 = 1.0 - pow(a->beta2, (double)t);
+  for (long i = 0; i < n; i++) {
+    m[i] = a->beta1 * m[i] + (1.0 - a->beta1) * gs[i];
+    v[i] = a->beta2 * v[i] + (1.0 - a->beta2) * gs[i] * gs[i];
+    double mh = m[i] / c1, vh = v[i] / c2;
+    du[i] = -a->lr * mh / (sqrt(vh) + a->eps);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* O6  Integration (Sec. 2.1, eq. compositive).  Reading: v = Delta u with   */
 /*     no further normalisation; u is resampled with the O1 conventions.     */
 /* ------------------------------------------------------------------------ */
@@ -579,7 +681,10 @@ int orc_attempt(const orc_params* p, const double* F, const double* M,
   double* v = (double*)malloc(sizeof(double) * 3 * N);
   double* ut = (double*)malloc(sizeof(double) * 3 * N);
   double* g = (double*)malloc(sizeof(double) * 3 * N);
-  orc_closed_form(gs, nz, ny, nx, r, s->lambda, v);
+  if (p->tile > 1)
+    orc_tile_step(gs, nz, ny, nx, p->tile, r, s->lambda, v);
+  else
+    orc_closed_form(gs, nz, ny, nx, r, s->lambda, v);
   orc_integrate(u, v, nz, ny, nx, p->step_eps, p->compositive, ut);
   double Lc = orc_loss_grad(F, M, ut, nz, ny, nx, p->window, p->cc_eps, g);
   int acc = orc_decide(p, s, Lc, force);
@@ -591,6 +696,28 @@ int orc_attempt(const orc_params* p, const double* F, const double* M,
   free(ut);
   free(g);
   return acc;
+}
+
+void orc_adam_iter(const orc_params* p, const orc_adam_params* a, const double* F,
+                   const double* M, double* u, double* gs, double* m, double* v,
+                   int nz, int ny, int nx, long t, orc_state* s) {
+  long N = (long)nz * ny * nx;
+  double* du = (double*)malloc(sizeof(double) * 3 * N);
+  double* ut = (double*)malloc(sizeof(double) * 3 * N);
+  double* g = (double*)malloc(sizeof(double) * 3 * N);
+  orc_adam_direction(gs, m, v, 3 * N, t, a, du);
+  orc_integrate(u, du, nz, ny, nx, p->step_eps, p->compositive, ut);
+  double L = orc_loss_grad(F, M, ut, nz, ny, nx, p->window, p->cc_eps, g);
+  orc_gauss(g, 3, nz, ny, nx, p->grad_sigma, gs);
+  memcpy(u, ut, sizeof(double) * 3 * N);
+  s->loss_prev = s->loss;
+  s->loss = L;
+  s->cand_loss = L;
+  s->n_hist += 1;
+  s->accepted = 1;
+  free(du);
+  free(ut);
+  free(g);
 }
 
 /* ------------------------------------------------------------------------ */

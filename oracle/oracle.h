@@ -34,7 +34,17 @@ typedef struct {
   double lambda_max;   /* cap of lambda (Sec. 3.4) */
   double tau;          /* rejection tolerance (eq. rejection); < 0 disables */
   int    max_retries;  /* consecutive rejections before a pair is frozen */
+  int    tile;         /* tile side k of the pooled Hessian (eq. tilen); 1 = eq. tile1 */
 } orc_params;
+
+/* Hyper-parameters of the Eulerian Adam comparator (the paper's baseline
+ * optimizer, Sec. 3: beta1 = 0.9, beta2 = 0.999). */
+typedef struct {
+  double lr;     /* step length eta in voxels */
+  double beta1;  /* first-moment decay */
+  double beta2;  /* second-moment decay */
+  double eps;    /* added to the root of the second moment */
+} orc_adam_params;
 
 /* Whole optimizer state of one pair: the scalar damping and a short loss
  * history (Sec. 2.2, "LM with rejection criterion"). */
@@ -98,6 +108,21 @@ void orc_closed_form(const double* gs, int nz, int ny, int nx, double r,
  * elimination with partial pivoting (eq. lm-local). */
 void orc_explicit_solve(const double g[3], double r, double lambda, double d[3]);
 
+/* O5' (eq. tilen): pooled Hessian of tile side k.  Tiles are the disjoint
+ * k^3 blocks of the grid starting at the origin (partial blocks at the far
+ * faces); H[t][6] = mean over the voxels of tile t of gs gs^T, entries
+ * (xx, yy, zz, xy, xz, yz).  Tiles are numbered x fastest. */
+void orc_tile_hessian(const double* gs, int nz, int ny, int nx, int k, double* H);
+/* O5' step: for every voxel, (H_tile + lambda I) du = -r gs by Gaussian
+ * elimination with partial pivoting (k = 1 gives eq. tile1). */
+void orc_tile_step(const double* gs, int nz, int ny, int nx, int k, double r,
+                   double lambda, double* du);
+
+/* Adam comparator: one bias-corrected Adam direction on gs at step t >= 1.
+ * m, v (3N) are updated in place; du = -lr mhat / (sqrt(vhat) + eps). */
+void orc_adam_direction(const double* gs, double* m, double* v, long n, long t,
+                        const orc_adam_params* a, double* du);
+
 /* O6: u_new = eps v + u o (Id + eps v)  (eq. compositive), or u + eps v. */
 void orc_integrate(const double* u, const double* v, int nz, int ny, int nx,
                    double eps, int compositive, double* unew);
@@ -115,6 +140,14 @@ void orc_begin(const orc_params* p, const double* F, const double* M,
 int orc_attempt(const orc_params* p, const double* F, const double* M,
                 double* u, double* gs, int nz, int ny, int nx,
                 orc_state* s, int force);
+
+/* One iteration of the Adam comparator: du from the moments of gs (step t),
+ * u <- eps du + u o (Id + eps du), then the loss and the smoothed gradient
+ * of the new field.  Every iteration is kept (no damping, no rejection);
+ * s->loss and s->cand_loss receive the new loss. */
+void orc_adam_iter(const orc_params* p, const orc_adam_params* a, const double* F,
+                   const double* M, double* u, double* gs, double* m, double* v,
+                   int nz, int ny, int nx, long t, orc_state* s);
 
 /* O8: average pooling by an integer factor (each dim divisible). */
 void orc_avgpool(const double* a, int nz, int ny, int nx, int f, double* out);
