@@ -9,13 +9,24 @@ in HBM before the timed region.  `value` is voxel-attempts per second over the
 timed steps: sum over levels of (voxels of the level x attempts evaluated).
 
 Printed on one JSON line, with
-  roofline      the dominant kernel of the full-resolution level: algorithmic
-                bytes per launch / its mean duration, measured with HIP events
-                the library records on its own stream inside the timed region;
-                traffic = HBM bytes per launch from the committed rocprofv3
-                counter summary when it was taken on the current kernel source;
+  roofline      one LM attempt at full resolution (its five kernels): the
+                method's algorithmic bytes (read F, M, u; write u~; write and
+                read the persisted smoothed gradient: 56 B per voxel with FP32
+                images, 52 with BF16) / the attempt's mean duration, the sum of
+                the kernels' mean durations measured with HIP events the
+                library records on its own stream inside the timed region;
+                traffic = HBM bytes per attempt from the committed rocprofv3
+                counter summaries when they were taken on the current kernel
+                sources; per_kernel gives each kernel's own figure against the
+                bytes its design reads and writes;
   cpu_baseline  the FP64 oracle on the host's cores on a bounded sample of the
-                same workload (attempts at the full-resolution level).
+                same workload (attempts at the full-resolution level, at the
+                host's thread count and at one thread; the whole 50-attempt run
+                of the 32^3 blob pair), with the CPU model;
+  detail        per-level attempts and losses; for the brain workload also the
+                learned initializer's time to the plain method's final LNCC on
+                16 held-out seeds and the attempt time at 384^3 with BF16
+                images (--no-extra skips both).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                     [--workload brain|lung|abdomen|batch] [--accum f64|f32c]
@@ -97,9 +108,26 @@ def traffic_for(kernel: str, workload: str):
     return float(d["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(F, M, attempts=2, what="the full-resolution level"):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(F, M, attempts=2, what="the full-resolution level", single_thread=True):
+    """The FP64 oracle on the host: `attempts` attempts on (F, M) at the
+    host's thread count (OMP_NUM_THREADS, else min(16, cpu_count)) and one at
+    one thread, plus the whole 50-attempt run of the 32^3 blob pair at both
+    thread counts."""
     import numpy as np
     import oracle
+    from paper_2603_19371_amd import phantoms
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
     oracle.set_threads(threads)
     used = oracle.get_threads()
@@ -112,10 +140,30 @@ def cpu_baseline(F, M, attempts=2, what="the full-resolution level"):
     t2 = time.perf_counter()
     n = int(np.prod(F.shape))
     sh = "x".join(str(d) for d in F.shape)
-    return {"value": n * attempts / (t2 - t1), "unit": "voxel-attempts/s",
-            "cores": used, "kind": "oracle",
-            "sample": f"{attempts} LM attempts of {what} ({sh}) after begin "
-                      f"({t1 - t0:.1f} s), FP64 oracle, {used} threads"}
+    out = {"value": n * attempts / (t2 - t1), "unit": "voxel-attempts/s",
+           "cores": used, "kind": "oracle",
+           "sample": f"{attempts} LM attempts of {what} ({sh}) after begin "
+                     f"({t1 - t0:.1f} s), FP64 oracle, {used} threads",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    if single_thread and used > 1:
+        oracle.set_threads(1)
+        t3 = time.perf_counter()
+        pr.attempt()
+        t4 = time.perf_counter()
+        out["single_thread_value"] = n / (t4 - t3)
+    # the 32^3 blob pair of the small configuration, its whole run
+    ph = phantoms.blobs((32, 32, 32), seed=0)
+    runs = {}
+    for th in sorted({1, used}):
+        oracle.set_threads(th)
+        t5 = time.perf_counter()
+        q = oracle.Pair(ph.F, ph.M, oracle.Params(window=5)).begin(lambda0=1.0)
+        for _ in range(50):
+            q.attempt()
+        runs[f"{th}_threads_s"] = round(time.perf_counter() - t5, 3)
+    out["blobs32_50_attempts"] = runs
+    oracle.set_threads(used)
+    return out
 
 
 def _pyramid_line(a, F, M, img_dtype, factors, iters, workload, s):
@@ -153,36 +201,111 @@ def _pyramid_line(a, F, M, img_dtype, factors, iters, workload, s):
     elapsed = t1 - t0
     nfine = int(np.prod(shape))
     kb = kernel_bytes(s)
-    dom = max((k for k in prof if prof[k]["count"]), key=lambda k: prof[k]["total_ms"])
-    achieved = kb[dom] * nfine / (prof[dom]["avg_ms"] * 1e-3) / 1e9
-    attempt_ms = sum(v["avg_ms"] for v in prof.values() if v["count"])
+    timed = {k: v for k, v in prof.items() if v["count"]}
+    attempt_ms = sum(v["avg_ms"] for v in timed.values())
+    # measured HBM bytes per launch (rocprofv3 counters, averaged over accepted
+    # and rejected attempts like the durations) while they match the sources
+    moved = {k: traffic_for(k, workload) for k in ("update", "lncc_fwd", "lncc_bwd", "smooth")}
+    complete = all(v is not None for v in moved.values())
+    ab = attempt_bytes(s) * nfine
+    achieved = ab / (attempt_ms * 1e-3) / 1e9
+    per_kernel = {}
+    for k, v in timed.items():
+        e = {"design_bytes_per_voxel": kb[k], "mean_ms": round(v["avg_ms"], 5),
+             "launches": v["count"]}
+        if kb[k]:
+            gbs = kb[k] * nfine / (v["avg_ms"] * 1e-3) / 1e9
+            e.update({"achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        if moved.get(k) is not None:
+            e["traffic"] = moved[k]
+        per_kernel[k] = e
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_for(dom, workload), "kernel": dom,
-                "algorithmic_bytes_per_launch": kb[dom] * nfine,
-                "mean_launch_ms": round(prof[dom]["avg_ms"], 5),
-                "launches_timed": prof[dom]["count"]}
+                "traffic": sum(moved.values()) if complete else None,
+                "kernel": "one full-resolution LM attempt (update, lncc_fwd, decide, "
+                          "lncc_bwd, smooth)",
+                "algorithmic_bytes_per_voxel": attempt_bytes(s),
+                "algorithmic_bytes_per_launch": ab,
+                "mean_launch_ms": round(attempt_ms, 5),
+                "launches_timed": max(v["count"] for v in timed.values()),
+                "dominant_kernel": max(timed, key=lambda k: timed[k]["total_ms"]),
+                "per_kernel": per_kernel}
     detail = {
         "levels": per_level,
-        "fine_level_kernel_ms": {k: round(v["avg_ms"], 5) for k, v in prof.items()
-                                 if v["count"]},
         "fine_level_attempt_ms": round(attempt_ms, 5),
         "fine_level_voxel_attempts_per_s": round(nfine / (attempt_ms * 1e-3), 1),
-        "fine_level_attempt_algorithmic_frac": round(
-            attempt_bytes(s) * nfine / (attempt_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernel_source_sha": source_sha(),
     }
-    # measured HBM bytes of a whole attempt (rocprofv3 counters of each kernel,
-    # per launch, averaged over accepted and rejected attempts like the
-    # durations) over the attempt's kernel time, while the counters match the
-    # current sources
-    moved = {k: traffic_for(k, workload) for k in ("update", "lncc_fwd", "lncc_bwd", "smooth")}
-    if all(v is not None for v in moved.values()):
-        t_ms = sum(prof[k]["avg_ms"] for k in moved if prof[k]["count"])
+    if complete:
         b = sum(moved.values())
+        t_ms = sum(prof[k]["avg_ms"] for k in moved if prof[k]["count"])
         detail["fine_level_attempt_hbm_bytes_per_voxel"] = round(b / nfine, 1)
         detail["fine_level_attempt_hbm_frac"] = round(b / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     return vox_att * a.steps / elapsed, elapsed, vox_att, roofline, detail
+
+
+def learned_detail(n_seeds=16):
+    """Time to the plain method's final LNCC (within 1e-3) on held-out seeds
+    5000.. with the committed network: plain coarse-to-fine LM vs prediction
+    + LM refinement, both gates (per-seed plain run; training-set median
+    folded count)."""
+    import numpy as np
+    from paper_2603_19371_amd import learned
+    base = os.path.join(ROOT, "paper_2603_19371_amd", "weights", "unet_brain160x192x224")
+    if not os.path.exists(base + ".npy"):
+        return {"skipped": "no committed weights"}
+    with open(base + ".json") as fh:
+        meta = json.load(fh)
+    sched = meta.get("schedule_selection", {}).get("chosen", "1:50")
+    schedule = [tuple(int(v) for v in st.split(":")) for st in sched.split(",")]
+    init = learned.LearnedInit(SHAPE, params=np.load(base + ".npy"))
+    t0 = time.perf_counter()
+    summary, _ = learned.evaluate(
+        init, range(5000, 5000 + n_seeds), schedule=schedule, ablation=False,
+        train_folded_median=meta.get("training", {}).get("plain_folded_median"),
+        log=lambda *_: None)
+    keys = ("seeds", "plain_ms_median", "plain_ms_p90", "learned_ms_median",
+            "learned_ms_p90", "learned_speedup_median", "learned_fallback_rate",
+            "learned_attempts_median", "learned_start_ms_median",
+            "learned_train_gate_speedup_median", "learned_train_gate_fallback_rate",
+            "plain_final_loss_median", "net_loss_median", "identity_loss_median",
+            "gate", "train_gate")
+    out = {k: (round(summary[k], 4) if isinstance(summary[k], float) else summary[k])
+           for k in keys if k in summary}
+    out.update({"schedule": sched, "held_out_seeds": f"5000..{5000 + n_seeds - 1}",
+                "wall_s": round(time.perf_counter() - t0, 1)})
+    return out
+
+
+def attempt_detail(shape=(384, 384, 384), attempts=20):
+    """Mean time of one LM attempt at `shape` with BF16 images (FP32 field,
+    FP64 loss) for both box-sum accumulators: a brain-like pair generated on
+    the device (the lung generator runs on the host, ~40 s at this size),
+    kernel times from HIP events on the context's stream."""
+    import torch
+    from paper_2603_19371_amd import _lib, phantoms_torch
+    F, M, _ = phantoms_torch.brain(shape, seed=0)
+    F, M = F.to(torch.bfloat16), M.to(torch.bfloat16)
+    n = F.numel()
+    out = {"shape": "x".join(map(str, shape)), "images": "bf16"}
+    for name, acc in ACCUM.items():
+        ctx = _lib.Context(shape, img_dtype=torch.bfloat16, window=WINDOW, grad_sigma=SIGMA,
+                           accum=acc)
+        ctx.begin(F, M, lambda0=1.0)
+        ctx.step(F, M, 5)
+        ctx.profile_start(max_attempts=attempts)
+        ctx.step(F, M, attempts)
+        prof = ctx.profile_stop()
+        ms = sum(v["avg_ms"] for v in prof.values() if v["count"])
+        out[name] = {"attempt_ms": round(ms, 4),
+                     "voxel_attempts_per_s": round(n / (ms * 1e-3), 1),
+                     "algorithmic_frac": round(attempt_bytes(2) * n / (ms * 1e-3) / 1e9
+                                               / HBM_PEAK_GBS, 4),
+                     "kernel_ms": {k: round(v["avg_ms"], 4) for k, v in prof.items()
+                                   if v["count"]}}
+        ctx.close()
+        torch.cuda.synchronize()
+    return out
 
 
 def run_brain(a):
@@ -195,6 +318,9 @@ def run_brain(a):
     workload = "brain160x192x224_f32_w7" + ("" if a.accum == "f64" else "_f32c")
     value, elapsed, vox_att, roofline, detail = _pyramid_line(
         a, F, M, torch.float32, FACTORS, ITERS, workload, 4)
+    if not a.no_extra:
+        detail["learned_init"] = learned_detail()
+        detail["attempt_384_bf16"] = attempt_detail()
     cpu = None if a.no_cpu_baseline else cpu_baseline(ph.F, ph.M)
     config = {"workload": "brain-MRI-like phantom 160x192x224, FP32 images and field, "
                           f"{ACCUM_TEXT[a.accum]}, LNCC w=7, sigma_g=1, pyramid 4x/2x/1x "
@@ -319,6 +445,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="brain workload: skip the learned-initializer and 384^3 legs")
     ap.add_argument("--workload", choices=("brain", "lung", "abdomen", "batch"),
                     default="brain")
     ap.add_argument("--accum", choices=tuple(ACCUM), default="f64",

@@ -86,6 +86,24 @@ lmr_status lmr_unet_backward(lmr_unet* net, const float* target, double target_s
 lmr_status lmr_unet_adam(lmr_unet* net, double lr, double beta1, double beta2,
                          double eps, double grad_scale);
 
+/* Test hook: layer `layer` alone, with the network's current (BF16-packed)
+ * weights, on the grid of the layer's level (dims >> level).  Checks each
+ * convolution of the forward and backward passes element by element.
+ *   x   device BF16 bits, channels last [N_l][ldx] (ldx >= cin, a multiple of
+ *       4, 8-byte aligned; channels cin..round4(cin)-1 must be finite);
+ *   y   (may be NULL) device FP32 [N_l][ldy], ldy >= cout: receives
+ *       act(conv(x) + b) before any rounding (act = ReLU except the head);
+ *   dz  (may be NULL) device BF16 [N_l][ldz] (ldz >= cout, a multiple of 4,
+ *       8-byte aligned): a gradient of the pre-activation output; then dW
+ *       [27][cin][cout] and db [cout] (device FP32) receive the parameter
+ *       gradients and dx (may be NULL; device BF16 [N_l][lddx], lddx >= cin)
+ *       the input gradient.
+ * The network's own activations and gradients are not touched.  Enqueues
+ * only.  LMR_EINVAL on a bad layer, pointer or stride. */
+lmr_status lmr_unet_layer_probe(lmr_unet* net, int layer, const uint16_t* x, int ldx,
+                                float* y, int ldy, const uint16_t* dz, int ldz,
+                                uint16_t* dx, int lddx, float* dW, float* db);
+
 #ifdef __cplusplus
 }
 #endif

@@ -139,6 +139,8 @@ def lib() -> C.CDLL:
             "lmr_unet_forward": (_I, [_V, _V, _V, _I, _I, _V]),
             "lmr_unet_backward": (_I, [_V, _V, _D, _I, _V]),
             "lmr_unet_adam": (_I, [_V, _D, _D, _D, _D, _D]),
+            "lmr_unet_layer_probe": (_I, [_V, _I, _V, _I, _V, _I, _V, _I, _V, _I, _V,
+                                          _V]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -164,7 +166,7 @@ def exported_symbols():
             "lmr_batch_destroy", "lmr_unet_param_count", "lmr_unet_layer_info",
             "lmr_unet_create", "lmr_unet_destroy", "lmr_unet_set_params",
             "lmr_unet_get_params", "lmr_unet_get_grads", "lmr_unet_forward",
-            "lmr_unet_backward", "lmr_unet_adam"]
+            "lmr_unet_backward", "lmr_unet_adam", "lmr_unet_layer_probe"]
 
 
 def _check(status: int, what: str):
@@ -376,6 +378,14 @@ class LevelView:
         enqueues the copy on it."""
         out = torch.empty((3,) + self.shape, device="cuda")
         _check(lib().lmr_get_field(self._h, out.data_ptr()), "lmr_get_field")
+        if sync:
+            _check(lib().lmr_get_state(self._h, C.byref(PairState())), "lmr_get_state")
+        return out
+
+    def grad(self, sync=True):
+        """Copy of the smoothed gradient of the accepted field (as field())."""
+        out = torch.empty((3,) + self.shape, device="cuda")
+        _check(lib().lmr_get_grad(self._h, out.data_ptr()), "lmr_get_grad")
         if sync:
             _check(lib().lmr_get_state(self._h, C.byref(PairState())), "lmr_get_state")
         return out
@@ -624,3 +634,28 @@ class UNet:
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=1.0):
         _check(lib().lmr_unet_adam(self._h, float(lr), float(beta1), float(beta2),
                                    float(eps), float(grad_scale)), "lmr_unet_adam")
+
+    def layer_probe(self, layer, x, dz=None):
+        """One layer alone (lmr_unet_layer_probe).  x: int16 CUDA tensor of
+        BF16 bits [N_l][ldx]; dz (optional) likewise [N_l][ldz].  Returns
+        (y FP32 [N_l][cout], dx BF16 bits [N_l][cin] or None, dW [27][cin][cout]
+        or None, db [cout] or None)."""
+        ci, co, _, _ = unet_layers()[layer]
+        n = x.shape[0]
+        for t, name in ((x, "x"),) + (((dz, "dz"),) if dz is not None else ()):
+            if not (t.is_cuda and t.dtype == torch.int16 and t.dim() == 2 and
+                    t.is_contiguous() and t.shape[0] == n):
+                raise LmrError(f"{name} must be a contiguous int16 CUDA tensor [N][ld]")
+        y = torch.empty((n, co), device="cuda")
+        dx = dW = db = None
+        if dz is not None:
+            dx = torch.empty((n, ci), dtype=torch.int16, device="cuda")
+            dW = torch.empty((27, ci, co), device="cuda")
+            db = torch.empty(co, device="cuda")
+        _check(lib().lmr_unet_layer_probe(
+            self._h, int(layer), x.data_ptr(), x.shape[1], y.data_ptr(), co,
+            dz.data_ptr() if dz is not None else None, dz.shape[1] if dz is not None else 0,
+            dx.data_ptr() if dx is not None else None, ci,
+            dW.data_ptr() if dW is not None else None,
+            db.data_ptr() if db is not None else None), "lmr_unet_layer_probe")
+        return y, dx, dW, db

@@ -401,6 +401,42 @@ lmr_status lmr_unet_backward(lmr_unet* u, const float* target, double target_sca
   return LMR_OK;
 }
 
+lmr_status lmr_unet_layer_probe(lmr_unet* u, int l, const uint16_t* x, int ldx, float* y,
+                                int ldy, const uint16_t* dz, int ldz, uint16_t* dx, int lddx,
+                                float* dW, float* db) {
+  if (!u || l < 0 || l >= LMR_UNET_LAYERS || !x) return LMR_EINVAL;
+  const LayerDef& L = kLayers[l];
+  if (ldx < L.cin || ldx % 4 || (reinterpret_cast<uintptr_t>(x) % 8)) return LMR_EINVAL;
+  if (y && ldy < L.cout) return LMR_EINVAL;
+  if (dz && (ldz < L.cout || ldz % 4 || (reinterpret_cast<uintptr_t>(dz) % 8) || !dW || !db))
+    return LMR_EINVAL;
+  if (dx && (!dz || lddx < L.cin)) return LMR_EINVAL;
+  const T xt{const_cast<uint16_t*>(x), ldx};
+  if (y) LMR_TRY(conv_fwd(u, l, xt, L.cin, T{nullptr, 0}, y, ldy));
+  if (dz) {
+    const int* d = u->dims[L.level];
+    LMR_TRY(unet_wgrad(x, ldx, L.cin, pad16(L.cin), dz, ldz, L.cout, pad16(L.cout), d[0],
+                       d[1], d[2], u->part, u->partb, dW, db, 0, u->stream));
+    if (dx) {
+      ConvArgs a{};
+      a.X = dz;
+      a.ldx = ldz;
+      a.cin_valid = L.cout;
+      a.cin_p = pad16(L.cout);
+      a.W = u->Wb[l];
+      a.cout = L.cin;
+      a.cout_p = pad16(L.cin);
+      a.Y = dx;
+      a.ldy = lddx;
+      a.nz = d[0];
+      a.ny = d[1];
+      a.nx = d[2];
+      LMR_TRY(unet_conv(a, u->stream));
+    }
+  }
+  return LMR_OK;
+}
+
 lmr_status lmr_unet_adam(lmr_unet* u, double lr, double beta1, double beta2, double eps,
                          double grad_scale) {
   if (!u || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) ||

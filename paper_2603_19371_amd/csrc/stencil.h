@@ -36,10 +36,15 @@ constexpr int kTX = 32;
 // sum hi + lo of two floats, accumulated by cascaded summation.  The high
 // parts add with Knuth's TwoSum, whose exact rounding error joins the low
 // parts, which add plainly; a product of two floats enters exactly through
-// the FMA remainder.  No renormalisation between additions: a box sum takes
-// at most a few dozen of them, so lo stays a few ulps of hi and hi + lo
-// carries about twice FP32's significand.  With contraction off the
-// sequences run as written.
+// the FMA remainder.  No renormalisation between additions.  The y- and
+// x-passes take 2R+1 additions each; the running z-sum of a tile takes two
+// per plane of its march (the entering plane and the leaving one), i.e.
+// 2 (cz + 2R) of them, about 200 on a 96-plane chunk.  Every TwoSum error is
+// at most half an ulp of the running hi, so after k additions |lo| is at
+// most about k/2 ulp(hi), and the plain additions of lo add an error of at
+// most k^2/4 * 2^-24 ulp(hi): below 0.01 ulp(hi) for k = 200.  hi + lo
+// therefore keeps about twice FP32's significand over a whole chunk.  With
+// contraction off the sequences run as written.
 struct F32C {
   float hi, lo;
   F32C() = default;  // trivial, so LDS arrays may hold it; F32C() value-initialises to 0

@@ -224,7 +224,7 @@ def _refine(init, pyr, fine, F, M, schedule, target):
 
 
 def evaluate(init: LearnedInit, seeds, schedule=((1, 50),), tol=1e-3, fold_frac=1e-4,
-             ablation=True, log=print):
+             ablation=True, train_folded_median=None, log=print):
     """Time to the plain method's final LNCC (within tol): plain coarse-to-fine
     LM from the identity vs prediction + LM refinement (`schedule`, ending
     with at most schedule[-1][1] attempts at full resolution).  With
@@ -237,7 +237,11 @@ def evaluate(init: LearnedInit, seeds, schedule=((1, 50),), tol=1e-3, fold_frac=
     every attempt and no host reads; the runs are bitwise identical, so the
     time to the target is the event time at that attempt.  A learned run that
     misses the target, or folds more than the plain run's count + fold_frac N
-    voxels, falls back to the plain method and is charged both."""
+    voxels, falls back to the plain method and is charged both (the per-seed
+    gate).  With train_folded_median the summary also reports the gate a
+    deployed pipeline can apply without a plain run of the same pair: the
+    folded count is compared with the median count of the plain method over
+    the training set (+ fold_frac N) instead."""
     shape = init.shape
     N = int(np.prod(shape))
     schedule = [tuple(st) for st in schedule]
@@ -287,6 +291,10 @@ def evaluate(init: LearnedInit, seeds, schedule=((1, 50),), tol=1e-3, fold_frac=
             losses, k, folded, t_start, t_end, begin_loss = _refine(
                 net, pyr, fine, F, M, schedule, target)
             ok = k is not None and folded <= plain_folded + fold_frac * N
+            if train_folded_median is not None:
+                ok_t = k is not None and folded <= train_folded_median + fold_frac * N
+                row[f"t_{tag}_train_gate_ms"] = t_end if ok_t else t_end + t_plain
+                row[f"{tag}_train_gate_fallback"] = not ok_t
             row.update({f"{tag}_begin_loss": begin_loss,
                         f"{tag}_final_loss": losses[-1],
                         f"{tag}_attempts": len(losses),
@@ -319,8 +327,19 @@ def evaluate(init: LearnedInit, seeds, schedule=((1, 50),), tol=1e-3, fold_frac=
             f"{tag}_attempts_median": float(np.median([r[f"{tag}_attempts"] for r in rows])),
             f"{tag}_start_ms_median": float(np.median([r[f"t_{tag}_start_ms"]
                                                        for r in rows]))})
+        if train_folded_median is not None:
+            tt = np.array([r[f"t_{tag}_train_gate_ms"] for r in rows])
+            summary.update({
+                f"{tag}_train_gate_ms_median": float(np.median(tt)),
+                f"{tag}_train_gate_speedup_median": float(np.median(tp) / np.median(tt)),
+                f"{tag}_train_gate_fallback_rate": float(np.mean(
+                    [r[f"{tag}_train_gate_fallback"] for r in rows]))})
     summary["gate"] = ("per-seed plain run (oracle gate): target = plain final loss + tol; "
                        "folded count <= plain count + fold_frac N")
+    if train_folded_median is not None:
+        summary["train_gate"] = ("target = plain final loss + tol; folded count <= "
+                                 f"training-set median plain count ({train_folded_median:g})"
+                                 " + fold_frac N")
     return summary, rows
 
 
@@ -368,7 +387,13 @@ def main(argv=None):
         lo, hi = (int(x) for x in a.seeds.split(":"))
         init = LearnedInit(shape, params=np.load(a.weights))
         sched = [tuple(int(v) for v in st.split(":")) for st in a.schedule.split(",")]
-        summary, rows = evaluate(init, range(lo, hi), schedule=sched, log=log)
+        meta_path = os.path.splitext(a.weights)[0] + ".json"
+        train_fold = None
+        if os.path.exists(meta_path):
+            with open(meta_path) as fh:
+                train_fold = json.load(fh).get("training", {}).get("plain_folded_median")
+        summary, rows = evaluate(init, range(lo, hi), schedule=sched,
+                                 train_folded_median=train_fold, log=log)
         with open(a.out, "w") as fh:
             json.dump(dict(summary=summary, rows=rows), fh, indent=1)
         log(json.dumps(summary))

@@ -1,4 +1,5 @@
-"""Batched persistent form: equivalence with per-pair runs and graph replays."""
+"""Batched persistent form: equivalence with per-pair runs and graph replays,
+and parity with the FP64 oracle at the shapes of the 16-pair workload."""
 import os
 
 import numpy as np
@@ -109,6 +110,60 @@ def test_autotuner_and_cache(L, pairs, tmp_path):
     b2.sync()
     for i in range(len(SHAPES)):
         assert b2.pair(i).state()["attempts"] == 3
+
+
+CONFIG4 = [(96, 96, 96), (128, 160, 128), (160, 192, 224), (192, 160, 256)]
+
+
+@pytest.fixture(scope="module")
+def config4():
+    """One brain-like pair of each shape of the 16-pair workload, and the FP64
+    oracle's begin and first automatic attempt on each (w = 7, sigma 1)."""
+    import oracle
+    from paper_2603_19371_amd import phantoms
+    oracle.set_threads(16)
+    out = []
+    for i, sh in enumerate(CONFIG4):
+        ph = phantoms.brain(sh, seed=100 + i)
+        pr = oracle.Pair(ph.F, ph.M, oracle.Params(window=7)).begin(lambda0=1.0)
+        acc = pr.attempt()
+        out.append((ph, pr, acc))
+        print(f"[config4 oracle] {sh}: accepted {acc}, loss {pr.state.loss:.9f}",
+              flush=True)
+    return out
+
+
+@pytest.mark.parametrize("tuned", [False, True])
+def test_batch_config4_shapes_match_oracle(L, config4, tuned):
+    """The four shapes advance in one persistent launch (graph replay), with
+    the default tiling and with the autotuner's choice.  After one automatic
+    attempt every pair has the oracle's decision and lambda, its loss within
+    2e-7, its field within 1e-4 voxel and the smoothed gradient of its
+    accepted field within 2e-5 of max|g|, element by element."""
+    Fs = [torch.from_numpy(ph.F).cuda() for ph, _, _ in config4]
+    Ms = [torch.from_numpy(ph.M).cuda() for ph, _, _ in config4]
+    b = L.Batch(CONFIG4, window=7)
+    if tuned:
+        b.tune(Fs, Ms, iters=1)
+    print(f"[config4] tiling {b.config()}", flush=True)
+    b.begin(Fs, Ms)
+    b.step(1, graph=True)
+    b.sync()
+    for i, (ph, pr, acc) in enumerate(config4):
+        v = b.pair(i)
+        st = v.state()
+        assert bool(st["accepted"]) == acc, i
+        assert st["lambda_"] == pr.state.lambda_, i
+        assert abs(st["loss"] - pr.state.loss) < 2e-7, (i, st["loss"], pr.state.loss)
+        u = host(v.field()).astype(np.float64)
+        eu = float(np.abs(u - pr.u).max())
+        gs = host(v.grad()).astype(np.float64)
+        eg = float(np.abs(gs - pr.gs).max())
+        gmax = float(np.abs(pr.gs).max())
+        print(f"[config4 {CONFIG4[i]} tuned={tuned}] field max|err| {eu:.3e}, "
+              f"g_smooth max|err| {eg:.3e} (max|g| {gmax:.3e})", flush=True)
+        assert eu < 1e-4, (i, eu)
+        assert eg < 2e-5 * gmax, (i, eg)
 
 
 def test_unsupported_gaussian_radius_is_rejected(L):

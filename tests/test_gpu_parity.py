@@ -412,34 +412,78 @@ def test_teacher_forced_bf16_images_compensated_fp32(L, orc):
     assert wl < 1e-6
 
 
-def test_lung_precision_form(L, orc):
-    """Precision form on a lung-CT-like pair (64^3, w = 7): BF16 images with
-    the FP32 field and the FP64 loss reduction.  Implementation: every
-    attempt of the oracle's trajectory restarted from the oracle's state
-    matches the oracle on the same BF16 values within 1e-4.  Precision
-    effect: the first attempt is within 5e-3 of the FP32-image oracle, and a
-    free two-level run (2x/1x, 20/10 attempts) ends within 2e-3 of the loss
-    of the FP32-image GPU run."""
-    from paper_2603_19371_amd.phantoms import bf16_to_f32, lung, to_bf16_rne
-    ph = lung((64, 64, 64), seed=2)
-    Fr, Mr = bf16_to_f32(to_bf16_rne(ph.F)), bf16_to_f32(to_bf16_rne(ph.M))
-    errs, _ = _teacher_forced(
-        L, orc, ph.F, ph.M, dev(Fr, torch.bfloat16), dev(Mr, torch.bfloat16),
-        torch.bfloat16, 10, [("lung bf16-images", Fr, Mr, 1e-4),
-                             ("lung fp32-images", ph.F, ph.M, 5e-3)], window=7)
-    assert max(errs["lung bf16-images"]) < 1e-4
-    assert errs["lung fp32-images"][0] < 5e-3
+LUNG = (384, 384, 384)
+
+
+@pytest.fixture(scope="module")
+def lung_full():
+    """The 384^3 lung-CT-like pair of the precision-form workload (seed 0)."""
+    from paper_2603_19371_amd.phantoms import lung
+    return lung(LUNG, seed=0)
+
+
+@pytest.mark.parametrize("accum", [0, 1])
+def test_lung_precision_form(L, orc, lung_full, accum):
+    """Precision form on the centred 64^3 crop of the 384^3 lung-CT-like pair
+    (w = 7): BF16 images, FP32 field, FP64 loss reduction, with FP64 box sums
+    (accum 0) and with compensated FP32 box sums (accum 1, the form as the
+    precision configuration states it).  Implementation: every attempt of
+    the oracle's trajectory restarted from the oracle's state matches the
+    oracle on the same BF16 values within 1e-4.  Precision effect: the first
+    attempt is within 5e-3 of the FP32-image oracle, and a free two-level run
+    (2x/1x, 20/10 attempts) ends within 2e-3 of the loss of the FP32-image
+    GPU run with FP64 sums."""
+    from paper_2603_19371_amd.phantoms import bf16_to_f32, to_bf16_rne
+    c = tuple(slice(d // 2 - 32, d // 2 + 32) for d in LUNG)
+    F = np.ascontiguousarray(lung_full.F[c])
+    M = np.ascontiguousarray(lung_full.M[c])
+    Fr, Mr = bf16_to_f32(to_bf16_rne(F)), bf16_to_f32(to_bf16_rne(M))
+    errs, wl = _teacher_forced(
+        L, orc, F, M, dev(Fr, torch.bfloat16), dev(Mr, torch.bfloat16),
+        torch.bfloat16, 10, [(f"lung crop bf16-images accum={accum}", Fr, Mr, 1e-4),
+                             (f"lung crop fp32-images accum={accum}", F, M, 5e-3)],
+        window=7, accum=accum)
+    assert max(errs[f"lung crop bf16-images accum={accum}"]) < 1e-4
+    assert errs[f"lung crop fp32-images accum={accum}"][0] < 5e-3
+    assert wl < 1e-6
     runs = {}
-    for name, F, M, dt in (("bf16", Fr, Mr, torch.bfloat16), ("fp32", ph.F, ph.M,
-                                                              torch.float32)):
-        pyr = L.Pyramid(ph.F.shape, (2, 1), img_dtype=dt, window=7)
-        u = host(pyr.run(dev(F, dt), dev(M, dt), [20, 10]))
+    for name, Fi, Mi, dt, acc in (("bf16", Fr, Mr, torch.bfloat16, accum),
+                                  ("fp32", F, M, torch.float32, 0)):
+        pyr = L.Pyramid(F.shape, (2, 1), img_dtype=dt, window=7, accum=acc)
+        u = host(pyr.run(dev(Fi, dt), dev(Mi, dt), [20, 10]))
         runs[name] = (u, pyr.level(1).state()["loss"])
     dL = abs(runs["bf16"][1] - runs["fp32"][1])
     du = float(np.abs(runs["bf16"][0] - runs["fp32"][0]).max())
-    print(f"[lung precision] final loss bf16 {runs['bf16'][1]:.6f} fp32 "
+    print(f"[lung precision accum={accum}] final loss bf16 {runs['bf16'][1]:.6f} fp32 "
           f"{runs['fp32'][1]:.6f} |dL| {dL:.2e}; field max|diff| {du:.3e}", flush=True)
     assert dL < 2e-3, dL
+
+
+def test_compensated_sums_on_long_chunks(L, orc, lung_full):
+    """Compensated FP32 box sums where the stencil tiles march long z-chunks
+    (384^3: 96 planes a chunk, about 200 additions per running sum): the
+    loss of the whole volume against the oracle within 2e-7, the cc map and
+    the raw gradient on sampled voxels within 2e-6 and 2e-5 of max|g|."""
+    ph = lung_full
+    u = (0.5 * ph.t).astype(np.float32)
+    ctx = L.Context(LUNG, window=7, accum=1)
+    loss, gr, _, cc = ctx.loss_grad(dev(ph.F), dev(ph.M), dev(u), smooth=False, cc=True)
+    orc.set_threads(16)
+    rL = -orc.lncc(ph.F, orc.warp(ph.M, u), 7, 1e-5)
+    print(f"[f32c 384^3 loss] gpu={loss:.12f} oracle={rL:.12f}", flush=True)
+    assert abs(loss - rL) < 2e-7
+    ccd, grd = host(cc), host(gr)
+    gmax = np.abs(grd).max()
+    F64, M64, u64 = (a.astype(np.float64) for a in (ph.F, ph.M, u))
+    worst_cc = worst_g = 0.0
+    for (z, y, x) in _samples(LUNG, 32, 9):
+        ecc = abs(ccd[z, y, x] - orc.cc_at(F64, M64, u64, 7, 1e-5, x, y, z))
+        eg = np.abs(grd[:, z, y, x] - orc.grad_at(F64, M64, u64, 7, 1e-5, x, y, z)).max()
+        worst_cc, worst_g = max(worst_cc, ecc), max(worst_g, eg)
+    print(f"[f32c 384^3 samples] cc max|err| {worst_cc:.3e}, g max|err| {worst_g:.3e} "
+          f"(max|g| {gmax:.3e})", flush=True)
+    assert worst_cc < 2e-6
+    assert worst_g < 2e-5 * gmax
 
 
 def test_checkpoint_resume_is_bitwise(L):
@@ -460,20 +504,35 @@ def test_checkpoint_resume_is_bitwise(L):
 
 
 def test_automatic_config1_run_tracks_oracle(L, orc):
-    """Unforced: the GPU takes its own decisions.  Ties between a candidate
-    and the accepted loss may be decided differently, so the test compares the
-    decision sequences and requires the same final loss to 1e-4."""
+    """Unforced: the GPU takes its own decisions over the 50 attempts of the
+    32^3 blob configuration.  The decision rule (eq. lambda-update,
+    eq. rejection) compares FP64 losses that differ between the FP32 kernels
+    and the FP64 oracle by ~1e-8, so a candidate within that of the accepted
+    loss may be decided differently; at most 2 of the 50 decisions may
+    differ.  The fields agree within 1e-4 voxel at every attempt up to the
+    first differing decision or attempt 10, whichever comes first (later, the
+    trilinear derivative's jumps at cell boundaries part any FP32 run from
+    the FP64 one), and the final loss within 1e-4."""
     ph = _config1(0)
     n = 50
-    pr, dec, _ = _oracle_run(orc, ph.F, ph.M, n, orc.Params(window=5))
+    pr = orc.Pair(ph.F, ph.M, orc.Params(window=5)).begin(lambda0=1.0)
     ctx = L.Context(ph.F.shape, window=5)
-    ctx.begin(dev(ph.F), dev(ph.M), lambda0=1.0)
-    gdec = []
+    Fd, Md = dev(ph.F), dev(ph.M)
+    ctx.begin(Fd, Md, lambda0=1.0)
+    dec, gdec, errs = [], [], []
     for _ in range(n):
-        ctx.step(dev(ph.F), dev(ph.M), 1)
+        dec.append(pr.attempt())
+        ctx.step(Fd, Md, 1)
         gdec.append(bool(ctx.state()["accepted"]))
-    mism = sum(a != b for a, b in zip(dec, gdec))
-    print(f"[auto] decision mismatches {mism}/{n}", flush=True)
+        errs.append(float(np.abs(host(ctx.field()) - pr.u).max()))
+    mism = [t for t in range(n) if dec[t] != gdec[t]]
+    first = mism[0] if mism else n
+    agree = min(first, 10)
+    print(f"[auto] decision mismatches {len(mism)}/{n} at {mism}; field max|err| over "
+          f"the first {agree} attempts {max(errs[:agree]):.3e}, at the end {errs[-1]:.3e}",
+          flush=True)
+    assert len(mism) <= 2, mism
+    assert max(errs[:agree]) < 1e-4
     st = ctx.state()
     assert abs(st["loss"] - pr.state.loss) < 1e-4
     assert st["attempts"] == n
