@@ -40,7 +40,7 @@ class _Params(C.Structure):
                 ("compositive", C.c_int), ("lambda_inc", C.c_double),
                 ("lambda_dec", C.c_double), ("lambda_min", C.c_double),
                 ("lambda_max", C.c_double), ("tau", C.c_double),
-                ("max_retries", C.c_int), ("tile", C.c_int)]
+                ("max_retries", C.c_int), ("tile", C.c_int), ("similarity", C.c_int)]
 
 
 class _Adam(C.Structure):
@@ -85,6 +85,8 @@ def lib():
             "orc_explicit_solve": (None, [_D, d, d, _D]),
             "orc_integrate": (None, [_D, _D, i, i, i, d, i, _D]),
             "orc_tile_hessian": (None, [_D, i, i, i, i, _D]),
+            "orc_mse_loss_grad": (d, [_D, _D, _D, i, i, i, _D]),
+            "orc_demons_step": (None, [_D, _D, _D, i, i, i, d, _D]),
             "orc_tile_step": (None, [_D, i, i, i, i, d, d, _D]),
             "orc_adam_direction": (None, [_D, _D, _D, l, l, C.POINTER(_Adam), _D]),
             "orc_adam_iter": (None, [C.POINTER(_Params), C.POINTER(_Adam), _D, _D, _D,
@@ -139,12 +141,13 @@ class Params:
     tau: float = 0.0
     max_retries: int = 10
     tile: int = 1
+    similarity: int = 0       # 0 LNCC, 1 squared error, 2 Demons step
 
     def c(self) -> _Params:
         return _Params(self.window, self.grad_sigma, self.cc_eps, self.step_eps,
                        self.compositive, self.lambda_inc, self.lambda_dec,
                        self.lambda_min, self.lambda_max, self.tau,
-                       self.max_retries, self.tile)
+                       self.max_retries, self.tile, self.similarity)
 
 
 @dataclass
@@ -237,6 +240,22 @@ def loss_grad(F, M, u, w, eps, with_grad=True):
     L = lib().orc_loss_grad(_p(F), _p(M), _p(u), *F.shape, int(w), float(eps),
                             _p(g) if with_grad else None)
     return (L, g) if with_grad else L
+
+
+def mse_loss_grad(F, M, u, with_grad=True):
+    """Returns (L, g_raw) with L = mean (F - M o (Id+u))^2 and g_raw = N dr/du,
+    r = sqrt(L)."""
+    F, M, u = _f64(F), _f64(M), _f64(u)
+    g = np.empty((3,) + F.shape) if with_grad else None
+    L = lib().orc_mse_loss_grad(_p(F), _p(M), _p(u), *F.shape, _p(g) if with_grad else None)
+    return (L, g) if with_grad else L
+
+
+def demons_step(F, M, u, lam):
+    F, M, u = _f64(F), _f64(M), _f64(u)
+    du = np.empty((3,) + F.shape)
+    lib().orc_demons_step(_p(F), _p(M), _p(u), *F.shape, float(lam), _p(du))
+    return du
 
 
 def grad_at(F, M, u, w, eps, x, y, z):

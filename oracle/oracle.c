@@ -472,6 +472,67 @@ void orc_explicit_solve(const double g[3], double r, double lambda,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Squared error and the Demons step (Sec. 2.2, the MSE needs no rewriting; */
+/* Sec. 2.3, eq. demons).  Readings: the single scalar residual of the MSE  */
+/* is r = sqrt(MSE), whose square is the loss (as 1 - LNCC is for LNCC),    */
+/* and the gradient the step uses is N dr/du; the Demons step field is      */
+/* Gaussian-smoothed with the gradient's sigma before eq. compositive.      */
+/* ------------------------------------------------------------------------ */
+
+double orc_mse_loss_grad(const double* F, const double* M, const double* u,
+                         int nz, int ny, int nx, double* g_raw) {
+  long N = (long)nz * ny * nx;
+  double* Mw = (double*)malloc(sizeof(double) * N);
+  double* dMw = (double*)malloc(sizeof(double) * 3 * N);
+  orc_warp(M, u, nz, ny, nx, Mw, dMw);
+  double s = 0.0;
+  for (long i = 0; i < N; i++) s += (F[i] - Mw[i]) * (F[i] - Mw[i]);
+  double L = s / (double)N;
+  if (g_raw) {
+    double r = sqrt(L);
+    for (long i = 0; i < N; i++) {
+      /* d r / d u_i = (1 / (2 r)) (2 / N) (Mw_i - F_i) dMw_i, times N */
+      double c = r > 0.0 ? (Mw[i] - F[i]) / r : 0.0;
+      for (int k = 0; k < 3; k++) g_raw[k * N + i] = c * dMw[k * N + i];
+    }
+  }
+  free(Mw);
+  free(dMw);
+  return L;
+}
+
+void orc_demons_step(const double* F, const double* M, const double* u, int nz,
+                     int ny, int nx, double lambda, double* du) {
+  long N = (long)nz * ny * nx;
+  double* Mw = (double*)malloc(sizeof(double) * N);
+  double* n = (double*)malloc(sizeof(double) * 3 * N);
+  orc_warp(M, u, nz, ny, nx, Mw, n);
+  for (long i = 0; i < N; i++) {
+    double r = F[i] - Mw[i];
+    double a = n[i], b = n[N + i], c = n[2 * N + i];
+    double den = a * a + b * b + c * c + lambda;
+    du[i] = r * a / den;
+    du[N + i] = r * b / den;
+    du[2 * N + i] = r * c / den;
+  }
+  free(Mw);
+  free(n);
+}
+
+/* The loss (and with g_raw the gradient the step uses) of the similarity. */
+static double sim_loss_grad(const orc_params* p, const double* F, const double* M,
+                            const double* u, int nz, int ny, int nx, double* g_raw) {
+  if (p->similarity == 0)
+    return orc_loss_grad(F, M, u, nz, ny, nx, p->window, p->cc_eps, g_raw);
+  return orc_mse_loss_grad(F, M, u, nz, ny, nx, g_raw);
+}
+
+/* The residual whose square is the minimised loss (Sec. 2.2). */
+static double residual(const orc_params* p, double L) {
+  return p->similarity == 0 ? 1.0 + L : sqrt(L > 0.0 ? L : 0.0);
+}
+
+/* ------------------------------------------------------------------------ */
 /* O5' Pooled Hessian over tiles of side k (Sec. 2.2, eq. tilen; Sec. 3.2).  */
 /*   Readings: the tiles are the disjoint k^3 blocks of the grid from the    */
 /*   origin (the ablation sweeps even sides too, so not a centred window);   */
@@ -656,7 +717,7 @@ void orc_begin(const orc_params* p, const double* F, const double* M,
                orc_state* s, double* gs_out) {
   long N = (long)nz * ny * nx;
   double* g = (double*)malloc(sizeof(double) * 3 * N);
-  double L = orc_loss_grad(F, M, u, nz, ny, nx, p->window, p->cc_eps, g);
+  double L = sim_loss_grad(p, F, M, u, nz, ny, nx, g);
   orc_gauss(g, 3, nz, ny, nx, p->grad_sigma, gs_out);
   free(g);
   s->lambda = lambda0;
@@ -677,16 +738,21 @@ int orc_attempt(const orc_params* p, const double* F, const double* M,
     return 0;
   }
   long N = (long)nz * ny * nx;
-  double r = 1.0 + s->loss; /* residual 1 - LNCC of the accepted field */
+  double r = residual(p, s->loss); /* e.g. 1 - LNCC of the accepted field */
   double* v = (double*)malloc(sizeof(double) * 3 * N);
   double* ut = (double*)malloc(sizeof(double) * 3 * N);
   double* g = (double*)malloc(sizeof(double) * 3 * N);
-  if (p->tile > 1)
+  if (p->similarity == 2) {
+    /* Demons: the per-voxel step of the accepted field, smoothed */
+    orc_demons_step(F, M, u, nz, ny, nx, s->lambda, g);
+    orc_gauss(g, 3, nz, ny, nx, p->grad_sigma, v);
+  } else if (p->tile > 1) {
     orc_tile_step(gs, nz, ny, nx, p->tile, r, s->lambda, v);
-  else
+  } else {
     orc_closed_form(gs, nz, ny, nx, r, s->lambda, v);
+  }
   orc_integrate(u, v, nz, ny, nx, p->step_eps, p->compositive, ut);
-  double Lc = orc_loss_grad(F, M, ut, nz, ny, nx, p->window, p->cc_eps, g);
+  double Lc = sim_loss_grad(p, F, M, ut, nz, ny, nx, g);
   int acc = orc_decide(p, s, Lc, force);
   if (acc) {
     memcpy(u, ut, sizeof(double) * 3 * N);
@@ -707,7 +773,7 @@ void orc_adam_iter(const orc_params* p, const orc_adam_params* a, const double* 
   double* g = (double*)malloc(sizeof(double) * 3 * N);
   orc_adam_direction(gs, m, v, 3 * N, t, a, du);
   orc_integrate(u, du, nz, ny, nx, p->step_eps, p->compositive, ut);
-  double L = orc_loss_grad(F, M, ut, nz, ny, nx, p->window, p->cc_eps, g);
+  double L = sim_loss_grad(p, F, M, ut, nz, ny, nx, g);
   orc_gauss(g, 3, nz, ny, nx, p->grad_sigma, gs);
   memcpy(u, ut, sizeof(double) * 3 * N);
   s->loss_prev = s->loss;

@@ -35,6 +35,7 @@ typedef struct {
   double tau;          /* rejection tolerance (eq. rejection); < 0 disables */
   int    max_retries;  /* consecutive rejections before a pair is frozen */
   int    tile;         /* tile side k of the pooled Hessian (eq. tilen); 1 = eq. tile1 */
+  int    similarity;   /* 0 LNCC, 1 squared error (MSE), 2 Demons step on the MSE */
 } orc_params;
 
 /* Hyper-parameters of the Eulerian Adam comparator (the paper's baseline
@@ -87,6 +88,15 @@ double orc_loss_grad(const double* F, const double* M, const double* u,
 void orc_grad_at(const double* F, const double* M, const double* u,
                  int nz, int ny, int nx, int w, double eps,
                  int x, int y, int z, double g[3]);
+
+/* Squared error (Sec. 2.2: already a squared loss): L = mean (F - Mw)^2 and
+ * g_raw = N dr/du with the scalar residual r = sqrt(L) (0 where r = 0). */
+double orc_mse_loss_grad(const double* F, const double* M, const double* u,
+                         int nz, int ny, int nx, double* g_raw);
+/* Demons step (Sec. 2.3, eq. demons): du_x = r_x n_x / (|n_x|^2 + lambda)
+ * with r_x = F - M o (Id + u) and n_x = grad M at x + u(x). */
+void orc_demons_step(const double* F, const double* M, const double* u, int nz,
+                     int ny, int nx, double lambda, double* du);
 
 /* O2 at one voxel: cc(x) of (F, M o (Id + u)), warping only the window. */
 double orc_cc_at(const double* F, const double* M, const double* u, int nz,
