@@ -40,7 +40,8 @@ class _Params(C.Structure):
                 ("compositive", C.c_int), ("lambda_inc", C.c_double),
                 ("lambda_dec", C.c_double), ("lambda_min", C.c_double),
                 ("lambda_max", C.c_double), ("tau", C.c_double),
-                ("max_retries", C.c_int), ("tile", C.c_int), ("similarity", C.c_int)]
+                ("max_retries", C.c_int), ("tile", C.c_int), ("similarity", C.c_int),
+                ("mi_bins", C.c_int)]
 
 
 class _Adam(C.Structure):
@@ -87,6 +88,9 @@ def lib():
             "orc_tile_hessian": (None, [_D, i, i, i, i, _D]),
             "orc_mse_loss_grad": (d, [_D, _D, _D, i, i, i, _D]),
             "orc_demons_step": (None, [_D, _D, _D, i, i, i, d, _D]),
+            "orc_mi_loss_grad": (d, [_D, _D, _D, i, i, i, i, _D, _D]),
+            "orc_bspline3": (d, [d]),
+            "orc_dbspline3": (d, [d]),
             "orc_tile_step": (None, [_D, i, i, i, i, d, d, _D]),
             "orc_adam_direction": (None, [_D, _D, _D, l, l, C.POINTER(_Adam), _D]),
             "orc_adam_iter": (None, [C.POINTER(_Params), C.POINTER(_Adam), _D, _D, _D,
@@ -141,13 +145,14 @@ class Params:
     tau: float = 0.0
     max_retries: int = 10
     tile: int = 1
-    similarity: int = 0       # 0 LNCC, 1 squared error, 2 Demons step
+    similarity: int = 0       # 0 LNCC, 1 squared error, 2 Demons step, 3 MI
+    mi_bins: int = 32
 
     def c(self) -> _Params:
         return _Params(self.window, self.grad_sigma, self.cc_eps, self.step_eps,
                        self.compositive, self.lambda_inc, self.lambda_dec,
                        self.lambda_min, self.lambda_max, self.tau,
-                       self.max_retries, self.tile, self.similarity)
+                       self.max_retries, self.tile, self.similarity, self.mi_bins)
 
 
 @dataclass
@@ -249,6 +254,26 @@ def mse_loss_grad(F, M, u, with_grad=True):
     g = np.empty((3,) + F.shape) if with_grad else None
     L = lib().orc_mse_loss_grad(_p(F), _p(M), _p(u), *F.shape, _p(g) if with_grad else None)
     return (L, g) if with_grad else L
+
+
+def mi_loss_grad(F, M, u, bins=32, with_grad=True, with_hist=False):
+    """Returns (L, g_raw[, hist]) with L = -MI (bits) of F and M o (Id + u)
+    and g_raw = N dr/du, r = log2(bins) - MI."""
+    F, M, u = _f64(F), _f64(M), _f64(u)
+    g = np.empty((3,) + F.shape) if with_grad else None
+    h = np.empty((bins, bins)) if with_hist else None
+    L = lib().orc_mi_loss_grad(_p(F), _p(M), _p(u), *F.shape, int(bins),
+                               _p(g) if with_grad else None, _p(h) if with_hist else None)
+    out = (L, g) if with_grad else (L,)
+    return out + ((h,) if with_hist else ()) if (with_hist or with_grad) else L
+
+
+def bspline3(t):
+    return lib().orc_bspline3(float(t))
+
+
+def dbspline3(t):
+    return lib().orc_dbspline3(float(t))
 
 
 def demons_step(F, M, u, lam):

@@ -519,17 +519,114 @@ void orc_demons_step(const double* F, const double* M, const double* u, int nz,
   free(n);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Mutual information (Sec. 2.2: (log2 B - MI)^2).  Readings: cubic B-spline */
+/* Parzen windows for both images (a partition of unity, so the fixed       */
+/* marginal does not depend on u); each image mapped to bin coordinates     */
+/* 1 + (B - 3)(v - lo)/(hi - lo) over its range (the moving range extended  */
+/* to 0, the value outside the volume), keeping every window inside the B   */
+/* bins; MI in bits; r = log2 B - MI and the step uses N dr/du.             */
+/* ------------------------------------------------------------------------ */
+
+double orc_bspline3(double t) {
+  double a = fabs(t);
+  if (a < 1.0) return 2.0 / 3.0 - a * a + 0.5 * a * a * a;
+  if (a < 2.0) return (2.0 - a) * (2.0 - a) * (2.0 - a) / 6.0;
+  return 0.0;
+}
+
+double orc_dbspline3(double t) {
+  double a = fabs(t), s = t < 0.0 ? -1.0 : 1.0;
+  if (a < 1.0) return s * (-2.0 * a + 1.5 * a * a);
+  if (a < 2.0) return -s * 0.5 * (2.0 - a) * (2.0 - a);
+  return 0.0;
+}
+
+static void range_of(const double* v, long n, int with_zero, double* lo, double* hi) {
+  double a = v[0], b = v[0];
+  for (long i = 1; i < n; i++) {
+    if (v[i] < a) a = v[i];
+    if (v[i] > b) b = v[i];
+  }
+  if (with_zero) {
+    if (a > 0.0) a = 0.0;
+    if (b < 0.0) b = 0.0;
+  }
+  if (!(b > a)) b = a + 1.0;
+  *lo = a;
+  *hi = b;
+}
+
+double orc_mi_loss_grad(const double* F, const double* M, const double* u, int nz,
+                        int ny, int nx, int B, double* g_raw, double* hist) {
+  long N = (long)nz * ny * nx;
+  double flo, fhi, mlo, mhi;
+  range_of(F, N, 0, &flo, &fhi);
+  range_of(M, N, 1, &mlo, &mhi);
+  double sf = (B - 3) / (fhi - flo), sm = (B - 3) / (mhi - mlo);
+  double* Mw = (double*)malloc(sizeof(double) * N);
+  double* dMw = (double*)malloc(sizeof(double) * 3 * N);
+  double* p = (double*)calloc((size_t)B * B, sizeof(double));
+  orc_warp(M, u, nz, ny, nx, Mw, dMw);
+  for (long i = 0; i < N; i++) {
+    double fh = 1.0 + (F[i] - flo) * sf, mh = 1.0 + (Mw[i] - mlo) * sm;
+    for (int a = 0; a < B; a++) {
+      double wa = orc_bspline3(fh - a);
+      if (wa == 0.0) continue;
+      for (int b = 0; b < B; b++) p[a * B + b] += wa * orc_bspline3(mh - b);
+    }
+  }
+  for (int k = 0; k < B * B; k++) p[k] /= (double)N;
+  double* pa = (double*)calloc(B, sizeof(double));
+  double* pb = (double*)calloc(B, sizeof(double));
+  for (int a = 0; a < B; a++)
+    for (int b = 0; b < B; b++) {
+      pa[a] += p[a * B + b];
+      pb[b] += p[a * B + b];
+    }
+  double mi = 0.0;
+  for (int a = 0; a < B; a++)
+    for (int b = 0; b < B; b++)
+      if (p[a * B + b] > 0.0) mi += p[a * B + b] * log2(p[a * B + b] / (pa[a] * pb[b]));
+  if (g_raw) {
+    for (long i = 0; i < N; i++) {
+      double fh = 1.0 + (F[i] - flo) * sf, mh = 1.0 + (Mw[i] - mlo) * sm;
+      double dmi = 0.0; /* d MI / d Mw_i, times N */
+      for (int a = 0; a < B; a++) {
+        double wa = orc_bspline3(fh - a);
+        if (wa == 0.0) continue;
+        for (int b = 0; b < B; b++) {
+          double pab = p[a * B + b];
+          if (pab <= 0.0) continue;
+          dmi += wa * orc_dbspline3(mh - b) * sm * log2(pab / pb[b]);
+        }
+      }
+      for (int k = 0; k < 3; k++) g_raw[k * N + i] = -dmi * dMw[k * N + i];
+    }
+  }
+  if (hist) memcpy(hist, p, sizeof(double) * B * B);
+  free(Mw);
+  free(dMw);
+  free(p);
+  free(pa);
+  free(pb);
+  return -mi;
+}
+
 /* The loss (and with g_raw the gradient the step uses) of the similarity. */
 static double sim_loss_grad(const orc_params* p, const double* F, const double* M,
                             const double* u, int nz, int ny, int nx, double* g_raw) {
   if (p->similarity == 0)
     return orc_loss_grad(F, M, u, nz, ny, nx, p->window, p->cc_eps, g_raw);
+  if (p->similarity == 3) return orc_mi_loss_grad(F, M, u, nz, ny, nx, p->mi_bins, g_raw, NULL);
   return orc_mse_loss_grad(F, M, u, nz, ny, nx, g_raw);
 }
 
 /* The residual whose square is the minimised loss (Sec. 2.2). */
 static double residual(const orc_params* p, double L) {
-  return p->similarity == 0 ? 1.0 + L : sqrt(L > 0.0 ? L : 0.0);
+  if (p->similarity == 0) return 1.0 + L;
+  if (p->similarity == 3) return log2((double)p->mi_bins) + L;
+  return sqrt(L > 0.0 ? L : 0.0);
 }
 
 /* ------------------------------------------------------------------------ */

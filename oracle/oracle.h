@@ -35,7 +35,9 @@ typedef struct {
   double tau;          /* rejection tolerance (eq. rejection); < 0 disables */
   int    max_retries;  /* consecutive rejections before a pair is frozen */
   int    tile;         /* tile side k of the pooled Hessian (eq. tilen); 1 = eq. tile1 */
-  int    similarity;   /* 0 LNCC, 1 squared error (MSE), 2 Demons step on the MSE */
+  int    similarity;   /* 0 LNCC, 1 squared error (MSE), 2 Demons step on the MSE,
+                          3 mutual information */
+  int    mi_bins;      /* B, the Parzen histogram's bins per image (>= 4) */
 } orc_params;
 
 /* Hyper-parameters of the Eulerian Adam comparator (the paper's baseline
@@ -93,6 +95,20 @@ void orc_grad_at(const double* F, const double* M, const double* u,
  * g_raw = N dr/du with the scalar residual r = sqrt(L) (0 where r = 0). */
 double orc_mse_loss_grad(const double* F, const double* M, const double* u,
                          int nz, int ny, int nx, double* g_raw);
+/* Mutual information (Sec. 2.2: minimise (log2 B - MI)^2) of F and
+ * M o (Id + u) from a joint histogram of B x B bins with cubic B-spline
+ * Parzen windows.  Each image's values are mapped to bin coordinates
+ * 1 + (B - 3)(v - lo)/(hi - lo) with [lo, hi] its range over the volume
+ * (the moving range extended to 0, the value outside the volume).
+ * Returns L = -MI (bits); g_raw (may be NULL) = N dr/du, r = log2 B - MI;
+ * hist (may be NULL) receives the joint probabilities [B][B] (fixed bin
+ * major). */
+double orc_mi_loss_grad(const double* F, const double* M, const double* u, int nz,
+                        int ny, int nx, int B, double* g_raw, double* hist);
+/* Cubic B-spline and its derivative (the Parzen window). */
+double orc_bspline3(double t);
+double orc_dbspline3(double t);
+
 /* Demons step (Sec. 2.3, eq. demons): du_x = r_x n_x / (|n_x|^2 + lambda)
  * with r_x = F - M o (Id + u) and n_x = grad M at x + u(x). */
 void orc_demons_step(const double* F, const double* M, const double* u, int nz,
