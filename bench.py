@@ -25,13 +25,15 @@ Printed on one JSON line, with
                 of the 32^3 blob pair), with the CPU model;
   detail        per-level attempts and losses; for the brain workload also the
                 learned initializer's time to the plain method's final LNCC on
-                16 held-out seeds and the attempt time at 384^3 with BF16
-                images (--no-extra skips both).
+                16 held-out seeds, the attempt time at 384^3 with BF16 images,
+                and device memory and time per iteration of the LM step and of
+                the Adam comparator on N^3 volumes, N = 64..512 (--no-extra
+                skips these).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--workload brain|lung|abdomen|batch] [--accum f64|f32c]
+                    [--workload brain|lung|abdomen|batch|unet] [--accum f64|f32c]
 
-The default workload is the brain registration above.  Three more workloads
+The default workload is the brain registration above.  Four more workloads
 print a line of the same form:
   lung     384^3 lung-CT-like pair with BF16 images (FP32 field, FP64 loss),
            pyramid 2x/1x with 100/50 attempts;
@@ -41,6 +43,9 @@ print a line of the same form:
            4 x 160x192x224, 4 x 192x160x256) advanced together, one persistent
            launch per attempt replayed from a HIP graph, tiling autotuned,
            150 attempts at full resolution.
+  unet     the learned initializer's network at 80x96x112: forward passes/s
+           and one training step, with its MFMA roofline (TFLOP/s of the 15
+           convolutions against 2.5 PFLOP/s BF16).
 --accum selects the LNCC box-sum accumulator: exact FP32 products summed in
 FP64 (default) or compensated FP32 pairs.
 """
@@ -308,6 +313,49 @@ def attempt_detail(shape=(384, 384, 384), attempts=20):
     return out
 
 
+def adam_vs_lm_detail(sides=(64, 128, 192, 256, 320, 384, 448, 512), attempts=10):
+    """Device memory and time per iteration of the LM step and of the Adam
+    comparator in the same kernels, on N^3 brain-like pairs generated on the
+    device (FP32 images, w = 7, sigma 1): the comparison of the paper's
+    Sec. 3.5.  Memory = the context's workspace + the two images; the drop
+    of free device memory when the context is created is reported beside
+    it."""
+    import torch
+    from paper_2603_19371_amd import _lib, phantoms_torch
+    rows = []
+    for n in sides:
+        shape = (n, n, n)
+        F, M, _ = phantoms_torch.brain(shape, seed=0)
+        del _
+        img = 2 * F.numel() * 4
+        row = {"N": n}
+        for name, opt in (("lm", 0), ("adam", 1)):
+            torch.cuda.synchronize()
+            free0 = torch.cuda.mem_get_info()[0]
+            ctx = _lib.Context(shape, window=WINDOW, grad_sigma=SIGMA, optimizer=opt)
+            torch.cuda.synchronize()
+            drop = free0 - torch.cuda.mem_get_info()[0]
+            ws = ctx.workspace_bytes()
+            ctx.begin(F, M, lambda0=1.0)
+            ctx.step(F, M, 3)
+            ctx.profile_start(max_attempts=attempts)
+            ctx.step(F, M, attempts)
+            prof = ctx.profile_stop()
+            ms = sum(v["avg_ms"] for v in prof.values() if v["count"])
+            row[name] = {"memory_MB": round((ws + img) / 1e6, 1),
+                         "workspace_bytes_per_voxel": round(ws / F.numel(), 2),
+                         "free_memory_drop_MB": round(drop / 1e6, 1),
+                         "iteration_ms": round(ms, 4)}
+            ctx.close()
+        row["memory_saved_pct"] = round(100.0 * (1 - row["lm"]["memory_MB"] /
+                                                 row["adam"]["memory_MB"]), 2)
+        row["speedup"] = round(row["adam"]["iteration_ms"] / row["lm"]["iteration_ms"], 3)
+        rows.append(row)
+        del F, M
+        torch.cuda.empty_cache()
+    return rows
+
+
 def run_brain(a):
     import torch
     from paper_2603_19371_amd import phantoms
@@ -321,6 +369,7 @@ def run_brain(a):
     if not a.no_extra:
         detail["learned_init"] = learned_detail()
         detail["attempt_384_bf16"] = attempt_detail()
+        detail["adam_vs_lm"] = adam_vs_lm_detail()
     cpu = None if a.no_cpu_baseline else cpu_baseline(ph.F, ph.M)
     config = {"workload": "brain-MRI-like phantom 160x192x224, FP32 images and field, "
                           f"{ACCUM_TEXT[a.accum]}, LNCC w=7, sigma_g=1, pyramid 4x/2x/1x "
@@ -439,6 +488,81 @@ def run_batch(a):
     return "f32", value, elapsed, config, roofline, cpu, detail
 
 
+def unet_flops(shape):
+    """Multiply-add FLOPs (2 per MAC) of the network's 15 convolutions at
+    `shape` (its own resolution): forward, and forward + backward (input
+    gradients of layers 1..14 and weight gradients of all)."""
+    from paper_2603_19371_amd import _lib
+    levels = (0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0)
+    fwd = bwd = 0
+    for l, (ci, co, _, _) in enumerate(_lib.unet_layers()):
+        n = 1
+        for d in shape:
+            n *= d >> levels[l]
+        f = 2 * n * 27 * ci * co
+        fwd += f
+        bwd += f * (2 if l else 1)
+    return fwd, fwd + bwd
+
+
+def run_unet(a):
+    """The learned initializer's network at 80x96x112 (half of the brain
+    shape): forward from a full-resolution pair (pooled by 2) and one training
+    step (forward, MSE backward, Adam), timed with HIP events."""
+    import numpy as np
+    import torch
+    from paper_2603_19371_amd import _lib, learned, phantoms_torch
+    shape = tuple(d // 2 for d in SHAPE)
+    F, M, t = phantoms_torch.brain(SHAPE, seed=5000)
+    net = _lib.UNet(shape)
+    base = os.path.join(ROOT, "paper_2603_19371_amd", "weights", "unet_brain160x192x224.npy")
+    params = np.load(base) if os.path.exists(base) else learned.init_params(0)
+    net.set_params(torch.from_numpy(params).cuda())
+    target = torch.nn.functional.avg_pool3d(t[None], 2)[0].contiguous()
+
+    def fwd():
+        net.forward(F, M, pool=True)
+
+    def train():
+        net.forward(F, M, pool=True)
+        net.backward(target, target_scale=0.5)
+        net.adam(1e-4)
+
+    out = {}
+    for name, fn in (("forward", fwd), ("training_step", train)):
+        for _ in range(max(a.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / a.steps
+    net.set_params(torch.from_numpy(params).cuda())   # leave the weights as loaded
+    f_fwd, f_train = unet_flops(shape)
+    tf = f_fwd / (out["forward"] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(tf, 2), "peak": 2500.0,
+                "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4), "traffic": None,
+                "kernel": "U-Net forward (15 BF16 MFMA convolutions with their epilogues, "
+                          "pooling, upsampling)",
+                "algorithmic_flops_per_launch": f_fwd,
+                "mean_launch_ms": round(out["forward"], 4), "launches_timed": a.steps}
+    detail = {"forward_ms": round(out["forward"], 4),
+              "training_step_ms": round(out["training_step"], 4),
+              "forward_gflop": round(f_fwd / 1e9, 2),
+              "training_step_gflop": round(f_train / 1e9, 2),
+              "training_step_tflops": round(f_train / (out["training_step"] * 1e-3) / 1e12, 2),
+              "kernel_source_sha": source_sha()}
+    config = {"workload": "learned initializer U-Net (16/32/64/128 channels, 3x3x3, BF16 MFMA, "
+                          "FP32 accumulation) at 80x96x112 on a brain-like pair pooled from "
+                          "160x192x224", "pairs": 1}
+    value = 1e3 / out["forward"]
+    return "bf16", value, a.steps * out["forward"] * 1e-3, config, roofline, None, detail
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -447,7 +571,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="brain workload: skip the learned-initializer and 384^3 legs")
-    ap.add_argument("--workload", choices=("brain", "lung", "abdomen", "batch"),
+    ap.add_argument("--workload", choices=("brain", "lung", "abdomen", "batch", "unet"),
                     default="brain")
     ap.add_argument("--accum", choices=tuple(ACCUM), default="f64",
                     help="box-sum accumulator of the LNCC passes")
@@ -458,13 +582,16 @@ def main():
         sys.exit(2)
 
     run = {"brain": run_brain, "lung": run_lung, "abdomen": run_abdomen,
-           "batch": run_batch}[a.workload]
+           "batch": run_batch, "unet": run_unet}[a.workload]
     dtype, value, elapsed, config, roofline, cpu, detail = run(a)
     line = {
-        "metric": "voxel-attempts/s of the LM step (full coarse-to-fine registration)"
-                  if a.workload != "batch" else
-                  "voxel-attempts/s of the LM step (batched pairs)",
-        "value": round(value, 1), "unit": "voxel-attempts/s", "n_gpus": 1,
+        "metric": {"batch": "voxel-attempts/s of the LM step (batched pairs)",
+                   "unet": "U-Net forward passes/s of the learned initializer"}.get(
+                       a.workload,
+                       "voxel-attempts/s of the LM step (full coarse-to-fine registration)"),
+        "value": round(value, 1),
+        "unit": "forward passes/s" if a.workload == "unet" else "voxel-attempts/s",
+        "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(elapsed / a.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

@@ -47,7 +47,7 @@ extern "C" {
 #endif
 
 #define LMR_VERSION_MAJOR 0
-#define LMR_VERSION_MINOR 1
+#define LMR_VERSION_MINOR 2
 
 typedef enum {
   LMR_OK = 0,
@@ -70,6 +70,40 @@ typedef enum { LMR_F32 = 0, LMR_BF16 = 1 } lmr_dtype;
  * the batched form included. */
 typedef enum { LMR_ACC_F64 = 0, LMR_ACC_F32C = 1 } lmr_accum;
 
+/* The optimizer of a context.  LMR_OPT_LM: the factored LM attempt (steps
+ * 1-5 above).  LMR_OPT_ADAM: the paper's baseline, Adam (Sec. 3, beta1 0.9,
+ * beta2 0.999) in the same kernels: the step is
+ *   du = -adam_lr mhat / (sqrt(vhat) + adam_eps)
+ * from bias-corrected moments of the smoothed gradient, integrated by
+ * eq. compositive like the LM step, and every step is kept (no damping, no
+ * rejection).  The moments add two FP32 fields (24 bytes per voxel) to the
+ * workspace: the memory the paper's Sec. 3.5 compares. */
+typedef enum { LMR_OPT_LM = 0, LMR_OPT_ADAM = 1 } lmr_optimizer;
+
+/* The similarity and its least-squares residual (Sec. 2.2).
+ * LMR_SIM_LNCC: L = -LNCC, r = 1 - LNCC (steps 1-5 above).
+ * LMR_SIM_MSE: L = mean (F - M o (Id + u))^2, already a squared loss: the
+ *   scalar residual is r = sqrt(L), the gradient g = N dr/du =
+ *   (Mw - F) grad Mw / r, smoothed and used as in step 1.
+ * LMR_SIM_DEMONS: the per-voxel form of the step on the squared error
+ *   (Sec. 2.3, eq. demons): du_x = r_x n_x / (|n_x|^2 + lambda) with
+ *   r_x = F(x) - M(x + u(x)) and n_x = grad M at x + u(x) of the accepted
+ *   field, lambda global and adapted by the same rules; the step field is
+ *   Gaussian-smoothed (grad_sigma) before eq. compositive.  LM only, tile 1.
+ * LMR_SIM_MI: mutual information of a mi_bins x mi_bins joint histogram with
+ *   cubic B-spline Parzen windows, each image mapped to bin coordinates
+ *   1 + (B - 3)(v - lo)/(hi - lo) over its range (the moving range extended
+ *   to 0); L = -MI (bits), r = log2 B - MI, g = N dr/du.  The histogram is
+ *   summed in fixed point (2^-32), so results do not depend on the order of
+ *   the additions.
+ * The loss of the decision is the similarity's L in every case. */
+typedef enum {
+  LMR_SIM_LNCC = 0,
+  LMR_SIM_MSE = 1,
+  LMR_SIM_DEMONS = 2,
+  LMR_SIM_MI = 3
+} lmr_similarity;
+
 /* Hyper-parameters of one registration.  The paper's own setting
  * (Sec. 3: lambda0 = 0.006, mu+ = 1.5, mu- = 0.975, no rejection) and the
  * synthetic-phantom setting (lambda x2 / x0.5, rejection with tau = 0) are
@@ -88,6 +122,18 @@ typedef struct {
   double lambda_max;   /* cap of lambda (Sec. 3.4); may be +inf */
   double tau;          /* rejection tolerance (eq. rejection); < 0 disables */
   int    max_retries;  /* consecutive rejections at lambda_max that freeze the pair */
+  int    tile;         /* side k of the tiles over which the rank-1 products are
+                          pooled (Sec. 2.2, eq. tilen; Sec. 3.2): each voxel
+                          solves (H_tile + lambda I) du = -r g with H_tile the
+                          mean of g g^T over its tile (disjoint k^3 blocks from
+                          the origin); 1 (default) = eq. tile1.  1..16 */
+  int    optimizer;    /* lmr_optimizer; LMR_OPT_ADAM requires tile = 1 */
+  double adam_lr;      /* Adam step length in voxels (> 0; default 0.1) */
+  double adam_beta1;   /* Adam decays, 0 <= beta < 1 (default 0.9, 0.999) */
+  double adam_beta2;
+  double adam_eps;     /* > 0 (default 1e-8) */
+  int    similarity;   /* lmr_similarity (default LMR_SIM_LNCC) */
+  int    mi_bins;      /* bins per image of LMR_SIM_MI, 8..32 (default 32) */
 } lmr_params;
 
 /* The whole optimizer state of one pair: the scalar damping and the loss
@@ -145,9 +191,13 @@ lmr_status lmr_step(lmr_ctx* ctx, const void* fixed, const void* moving,
 /* As lmr_step, with the accept/reject decision of attempt i forced to
  * decisions[i] (host array; 1 accept, 0 reject, -1 automatic).  Lambda and
  * the loss history follow the forced decision exactly as they would follow
- * an automatic one.  Used to replay a recorded trajectory. */
+ * an automatic one.  Used to replay a recorded trajectory.  An Adam context
+ * keeps every step: a forced rejection gives LMR_EINVAL. */
 lmr_status lmr_step_forced(lmr_ctx* ctx, const void* fixed, const void* moving,
                            const int* decisions, int n);
+
+/* Bytes of device memory the context holds (its whole workspace). */
+lmr_status lmr_workspace_bytes(const lmr_ctx* ctx, size_t* out);
 
 /* Copies the accepted field into field_out (device, [3][nz][ny][nx]). */
 lmr_status lmr_get_field(lmr_ctx* ctx, float* field_out);
@@ -160,7 +210,8 @@ lmr_status lmr_get_state(lmr_ctx* ctx, lmr_pair_state* out);
  * a registration from a checkpoint (lmr_get_field + lmr_get_state); the
  * resumed attempts are bitwise identical to the uninterrupted ones when `in`
  * holds the saved state.  Requires lambda > 0 and n_hist >= 1.  Asynchronous
- * (the struct is copied before the call returns). */
+ * (the struct is copied before the call returns).  LMR_EINVAL on an Adam
+ * context (its moments are part of its state and are not restored here). */
 lmr_status lmr_set_state(lmr_ctx* ctx, const lmr_pair_state* in);
 
 /* Test hook: loss and gradients of an arbitrary field u (device) without
@@ -173,7 +224,10 @@ lmr_status lmr_loss_grad(lmr_ctx* ctx, const void* fixed, const void* moving,
                          float* g_smooth, float* cc_map);
 
 /* Test hook: steps 1-2 alone.  u_out = eps du + u o (Id + eps du) with
- * du = -r g / (|g|^2 + lambda) (device arrays, [3][nz][ny][nx]). */
+ * du = -r g / (|g|^2 + lambda) (device arrays, [3][nz][ny][nx]), or with
+ * tile > 1 du = -r (H_tile + lambda I)^-1 g, H_tile pooled from g_smooth
+ * (the context's tile workspace is overwritten).  LMR_EINVAL on an Adam
+ * context. */
 lmr_status lmr_update(lmr_ctx* ctx, const float* u, const float* g_smooth,
                       double r, double lambda, float* u_out);
 

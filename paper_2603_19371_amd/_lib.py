@@ -37,7 +37,10 @@ class Params(C.Structure):
                 ("compositive", C.c_int), ("accum", C.c_int),
                 ("lambda_inc", C.c_double), ("lambda_dec", C.c_double),
                 ("lambda_min", C.c_double), ("lambda_max", C.c_double),
-                ("tau", C.c_double), ("max_retries", C.c_int)]
+                ("tau", C.c_double), ("max_retries", C.c_int),
+                ("tile", C.c_int), ("optimizer", C.c_int), ("adam_lr", C.c_double),
+                ("adam_beta1", C.c_double), ("adam_beta2", C.c_double),
+                ("adam_eps", C.c_double), ("similarity", C.c_int), ("mi_bins", C.c_int)]
 
     @staticmethod
     def make(**kw) -> "Params":
@@ -94,6 +97,7 @@ def lib() -> C.CDLL:
             "lmr_step": (_I, [_V, _V, _V, _I]),
             "lmr_step_forced": (_I, [_V, _V, _V, C.POINTER(_I), _I]),
             "lmr_get_field": (_I, [_V, _V]),
+            "lmr_workspace_bytes": (_I, [_V, C.POINTER(C.c_size_t)]),
             "lmr_get_grad": (_I, [_V, _V]),
             "lmr_get_state": (_I, [_V, C.POINTER(PairState)]),
             "lmr_loss_grad": (_I, [_V, _V, _V, _V, C.POINTER(_D), _V, _V, _V]),
@@ -156,6 +160,7 @@ def exported_symbols():
     return ["lmr_strerror", "lmr_last_error", "lmr_default_params", "lmr_create",
             "lmr_destroy", "lmr_begin", "lmr_step", "lmr_step_forced",
             "lmr_get_field", "lmr_get_grad", "lmr_get_state", "lmr_loss_grad",
+            "lmr_workspace_bytes",
             "lmr_update", "lmr_warp", "lmr_decide_probe", "lmr_smooth",
             "lmr_set_state", "lmr_kernel_name", "lmr_profile_start",
             "lmr_profile_stop", "lmr_avgpool", "lmr_upsample_field",
@@ -252,6 +257,11 @@ class Context:
                                                       device="cuda")
         _check(lib().lmr_get_field(self._h, self._field(out, "out")), "lmr_get_field")
         return out
+
+    def workspace_bytes(self) -> int:
+        n = C.c_size_t()
+        _check(lib().lmr_workspace_bytes(self._h, C.byref(n)), "lmr_workspace_bytes")
+        return n.value
 
     def grad(self, out=None):
         out = out if out is not None else torch.empty((3,) + self.shape,

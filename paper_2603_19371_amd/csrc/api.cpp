@@ -36,7 +36,44 @@ bool lmr::params_ok(const lmr_params* p) {
   if (!(p->lambda_inc > 1.0) || !(p->lambda_dec > 0.0 && p->lambda_dec < 1.0)) return false;
   if (!(p->lambda_min > 0.0) || !(p->lambda_max >= p->lambda_min)) return false;
   if (p->max_retries < 1) return false;
+  if (p->tile < 1 || p->tile > 16) return false;
+  if (p->optimizer != LMR_OPT_LM && p->optimizer != LMR_OPT_ADAM) return false;
+  if (p->similarity != LMR_SIM_LNCC && p->similarity != LMR_SIM_MSE &&
+      p->similarity != LMR_SIM_DEMONS && p->similarity != LMR_SIM_MI)
+    return false;
+  if (p->similarity == LMR_SIM_MI && (p->mi_bins < 8 || p->mi_bins > 32)) return false;
+  if (p->similarity == LMR_SIM_DEMONS && (p->optimizer != LMR_OPT_LM || p->tile != 1))
+    return false;
+  if (p->optimizer == LMR_OPT_ADAM) {
+    if (p->tile != 1 || !(p->adam_lr > 0.0) || !(p->adam_eps > 0.0)) return false;
+    if (!(p->adam_beta1 >= 0.0 && p->adam_beta1 < 1.0)) return false;
+    if (!(p->adam_beta2 >= 0.0 && p->adam_beta2 < 1.0)) return false;
+  }
   return true;
+}
+
+lmr::StepExtra lmr_ctx::extra() const {
+  lmr::StepExtra x{};
+  if (p.similarity == LMR_SIM_DEMONS) {
+    x.mode = 3;
+  } else if (p.optimizer == LMR_OPT_ADAM) {
+    x.mode = 2;
+    x.m = am;
+    x.v = av;
+    x.b1 = static_cast<float>(p.adam_beta1);
+    x.ob1 = static_cast<float>(1.0 - p.adam_beta1);
+    x.b2 = static_cast<float>(p.adam_beta2);
+    x.ob2 = static_cast<float>(1.0 - p.adam_beta2);
+    x.lr = static_cast<float>(p.adam_lr);
+    x.aeps = static_cast<float>(p.adam_eps);
+  } else if (p.tile > 1) {
+    x.mode = 1;
+    x.H = H;
+    x.k = p.tile;
+    x.tx = tiles[0];
+    x.ty = tiles[1];
+  }
+  return x;
 }
 
 namespace {
@@ -44,6 +81,9 @@ namespace {
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
 // One attempt: P1 update, P2 forward, P3 decide, P4 backward, P5 smooth.
+// Squared error: P2 is the squared-error reduction and P4 its gradient.
+// Demons: the step field is formed and smoothed before P1 (timed with P1),
+// and P4 keeps the residuals of an accepted field (no P5).
 lmr_status enqueue_attempt(lmr_ctx* c, const void* F, const void* M, int force) {
   hipStream_t s = c->stream;
   Profiler& pr = c->prof;
@@ -56,26 +96,53 @@ lmr_status enqueue_attempt(lmr_ctx* c, const void* F, const void* M, int force) 
   auto mark = [&](int k, int end) -> hipError_t {
     return ev ? hipEventRecord(ev[2 * k + end], s) : hipSuccess;
   };
+  const int sim = c->p.similarity;
+  // the Adam comparator keeps every step
+  if (c->p.optimizer == LMR_OPT_ADAM) force = 1;
+  const StepExtra ex = c->extra();
   LMR_HIP(mark(LMR_K_UPDATE, 0));
+  if (sim == LMR_SIM_DEMONS) {
+    // du from the kept residuals of the accepted field, smoothed into G
+    LMR_HIP(launch_demons_force(c->maps, c->g, c->st, c->graw, s));
+    LMR_HIP(launch_smooth(c->graw, c->g, c->p, nullptr, c->G, s));
+  }
   // the derivative of the candidate's warped image goes to graw, where P4
   // reads it (voxel by voxel, before overwriting it with the raw gradient)
   LMR_HIP(launch_update(M, c->img, c->g, c->p, c->st, c->G, c->U[0], c->U[1], nullptr,
-                        nullptr, 0.0, 0.0, c->Mw, c->graw, s));
+                        nullptr, 0.0, 0.0, c->Mw, c->graw, s, &ex));
   LMR_HIP(mark(LMR_K_UPDATE, 1));
   LMR_HIP(mark(LMR_K_FWD, 0));
-  LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, c->st, c->maps, c->partials,
-                     nullptr, s));
+  if (sim == LMR_SIM_LNCC)
+    LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, c->st, c->maps, c->partials,
+                       nullptr, s));
+  else if (sim == LMR_SIM_MI)
+    LMR_HIP(launch_mi_fwd(F, c->img, c->Mw, c->g, c->p.mi_bins, c->mi_map, c->mi_hpart,
+                          c->mi_p, c->mi_tab, c->partials, c->st, s));
+  else
+    LMR_HIP(launch_mse_fwd(F, c->img, c->Mw, c->g, c->nparts, c->partials, nullptr, c->st, s));
   LMR_HIP(mark(LMR_K_FWD, 1));
   LMR_HIP(mark(LMR_K_DECIDE, 0));
-  LMR_HIP(launch_decide(c->st, c->partials, c->nparts, c->g.N, c->dp, 0, force, 0.0,
-                        nullptr, s));
+  LMR_HIP(launch_decide(c->st, c->partials, sim == LMR_SIM_MI ? 1 : c->nparts, c->g.N, c->dp,
+                        0, force, 0.0, nullptr, s));
   LMR_HIP(mark(LMR_K_DECIDE, 1));
   LMR_HIP(mark(LMR_K_BWD, 0));
-  LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, c->st, c->U[0], c->U[1],
-                     nullptr, c->graw, c->graw, s));
+  if (sim == LMR_SIM_LNCC)
+    LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, c->st, c->U[0], c->U[1],
+                       nullptr, c->graw, c->graw, s));
+  else if (sim == LMR_SIM_MSE)
+    LMR_HIP(launch_mse_bwd(F, c->img, c->Mw, c->graw, c->g, c->st, nullptr, c->graw, s));
+  else if (sim == LMR_SIM_MI)
+    LMR_HIP(launch_mi_bwd(F, c->img, c->Mw, c->graw, c->g, c->p.mi_bins, c->mi_map, c->mi_tab,
+                          c->st, c->graw, s));
+  else
+    LMR_HIP(launch_demons_keep(F, c->img, c->Mw, c->graw, c->g, c->st, c->maps, s));
   LMR_HIP(mark(LMR_K_BWD, 1));
   LMR_HIP(mark(LMR_K_SMOOTH, 0));
-  LMR_HIP(launch_smooth(c->graw, c->g, c->p, c->st, c->G, s));
+  if (sim != LMR_SIM_DEMONS) {
+    LMR_HIP(launch_smooth(c->graw, c->g, c->p, c->st, c->G, s));
+    // eq. tilen: the pooled matrices of the new gradient (timed with P5)
+    if (ex.mode == 1) LMR_HIP(launch_tile_hessian(c->G, c->g, c->p.tile, c->H, c->st, 2, s));
+  }
   LMR_HIP(mark(LMR_K_SMOOTH, 1));
   return LMR_OK;
 }
@@ -118,6 +185,14 @@ void lmr_default_params(lmr_params* p) {
   p->lambda_max = 1e6;
   p->tau = 0.0;
   p->max_retries = 10;
+  p->tile = 1;
+  p->optimizer = LMR_OPT_LM;
+  p->adam_lr = 0.1;
+  p->adam_beta1 = 0.9;
+  p->adam_beta2 = 0.999;
+  p->adam_eps = 1e-8;
+  p->similarity = LMR_SIM_LNCC;
+  p->mi_bins = 32;
 }
 
 lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
@@ -135,8 +210,10 @@ lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
   c->g = Geom{nz, ny, nx, N};
   c->img = img;
   c->p = *p;
-  c->dp = DecideParams{p->lambda_inc, p->lambda_dec, p->lambda_min, p->lambda_max,
-                       p->tau, p->max_retries};
+  c->dp = DecideParams{p->lambda_inc, p->lambda_dec,     p->lambda_min,
+                       p->lambda_max, p->tau,            p->max_retries,
+                       p->adam_beta1, p->adam_beta2,     p->similarity,
+                       p->mi_bins};
   c->stream = stream;
   c->nparts = fwd_num_blocks(c->g, p->window);
 
@@ -154,8 +231,23 @@ lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
                           align256(sizeof(double)),
                           align256(sizeof(unsigned long long)),
                           align256(sizeof(double) * 2 * N)};
-  size_t total = 0;
+  const int k = p->tile;
+  c->tiles[0] = (nx + k - 1) / k;
+  c->tiles[1] = (ny + k - 1) / k;
+  c->tiles[2] = (nz + k - 1) / k;
+  const size_t h_bytes =
+      k > 1 ? align256(sizeof(double) * 6 * (size_t)c->tiles[0] * c->tiles[1] * c->tiles[2])
+            : 0;
+  const size_t mv_bytes = p->optimizer == LMR_OPT_ADAM ? f3 : 0;
+  const bool mi = p->similarity == LMR_SIM_MI;
+  const size_t bb = mi ? static_cast<size_t>(p->mi_bins) * p->mi_bins : 0;
+  const size_t mi_sizes[5] = {align256(8 * bb * kMiBlocks), align256(8 * bb), align256(8 * bb),
+                              mi ? align256(32) : 0, mi ? align256(16 * kMiBlocks) : 0};
+  size_t mi_bytes = 0;
+  for (size_t v : mi_sizes) mi_bytes += v;
+  size_t total = h_bytes + 2 * mv_bytes + mi_bytes;
   for (size_t s : sizes) total += s;
+  c->arena_bytes = total;
   hipError_t e = hipMalloc(&c->arena, total);
   if (e != hipSuccess) {
     snprintf(g_err, sizeof g_err, "%s", hipGetErrorString(e));
@@ -175,7 +267,24 @@ lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
   c->st_probe = reinterpret_cast<DevState*>(q); q += sizes[9];
   c->part_probe = reinterpret_cast<double*>(q); q += sizes[10];
   c->counter = reinterpret_cast<unsigned long long*>(q);
-  c->fstat = reinterpret_cast<double*>(q + sizes[11]);
+  q += sizes[11];
+  c->fstat = reinterpret_cast<double*>(q);
+  q += sizes[12];
+  c->H = h_bytes ? reinterpret_cast<double*>(q) : nullptr;
+  q += h_bytes;
+  c->am = mv_bytes ? reinterpret_cast<float*>(q) : nullptr;
+  c->av = mv_bytes ? reinterpret_cast<float*>(q + mv_bytes) : nullptr;
+  q += 2 * mv_bytes;
+  c->mi_hpart = mi ? reinterpret_cast<unsigned long long*>(q) : nullptr;
+  q += mi_sizes[0];
+  c->mi_p = mi ? reinterpret_cast<double*>(q) : nullptr;
+  q += mi_sizes[1];
+  c->mi_tab = mi ? reinterpret_cast<double*>(q) : nullptr;
+  q += mi_sizes[2];
+  c->mi_map = mi ? reinterpret_cast<double*>(q) : nullptr;
+  q += mi_sizes[3];
+  c->mi_rpart = mi ? reinterpret_cast<float*>(q) : nullptr;
+  c->mi_of[0] = c->mi_of[1] = nullptr;
   c->begun = false;
   *out = c;
   return LMR_OK;
@@ -198,16 +307,47 @@ lmr_status lmr_begin(lmr_ctx* c, const void* F, const void* M, const float* fiel
     LMR_HIP(hipMemcpyAsync(c->U[0], field, bytes, hipMemcpyDeviceToDevice, s));
   else
     LMR_HIP(launch_fill(c->U[0], 3 * c->g.N, 0.0f, s));
-  LMR_HIP(launch_fstat(F, c->img, c->g, c->p, c->fstat, s));
-  c->fstat_of = F;
-  LMR_HIP(launch_warp(M, c->img, c->U[0], c->g, c->Mw, nullptr, s));
-  LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, nullptr, c->maps,
-                     c->partials, nullptr, s));
-  LMR_HIP(launch_decide(c->st, c->partials, c->nparts, c->g.N, c->dp, 1, -1, lambda0,
-                        nullptr, s));
-  LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, nullptr, nullptr,
-                     nullptr, c->U[0], nullptr, c->graw, s));
-  LMR_HIP(launch_smooth(c->graw, c->g, c->p, nullptr, c->G, s));
+  const int sim = c->p.similarity;
+  if (sim == LMR_SIM_LNCC) {
+    LMR_HIP(launch_fstat(F, c->img, c->g, c->p, c->fstat, s));
+    c->fstat_of = F;
+    LMR_HIP(launch_warp(M, c->img, c->U[0], c->g, c->Mw, nullptr, s));
+    LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, nullptr, c->maps,
+                       c->partials, nullptr, s));
+  } else if (sim == LMR_SIM_MI) {
+    LMR_HIP(launch_mi_range(F, M, c->img, c->g, c->p.mi_bins, c->mi_rpart, c->mi_map, s));
+    c->mi_of[0] = F;
+    c->mi_of[1] = M;
+    LMR_HIP(launch_warp(M, c->img, c->U[0], c->g, c->Mw, c->graw, s));
+    LMR_HIP(launch_mi_fwd(F, c->img, c->Mw, c->g, c->p.mi_bins, c->mi_map, c->mi_hpart,
+                          c->mi_p, c->mi_tab, c->partials, nullptr, s));
+  } else {
+    LMR_HIP(launch_warp(M, c->img, c->U[0], c->g, c->Mw, c->graw, s));
+    LMR_HIP(launch_mse_fwd(F, c->img, c->Mw, c->g, c->nparts, c->partials, nullptr, nullptr,
+                           s));
+  }
+  LMR_HIP(launch_decide(c->st, c->partials, sim == LMR_SIM_MI ? 1 : c->nparts, c->g.N, c->dp,
+                        1, -1, lambda0, nullptr, s));
+  if (sim == LMR_SIM_LNCC) {
+    LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, nullptr, nullptr,
+                       nullptr, c->U[0], nullptr, c->graw, s));
+    LMR_HIP(launch_smooth(c->graw, c->g, c->p, nullptr, c->G, s));
+  } else if (sim == LMR_SIM_MSE) {
+    // the state holds r = sqrt(L) of the starting field
+    LMR_HIP(launch_mse_bwd(F, c->img, c->Mw, c->graw, c->g, c->st, nullptr, c->graw, s));
+    LMR_HIP(launch_smooth(c->graw, c->g, c->p, nullptr, c->G, s));
+  } else if (sim == LMR_SIM_MI) {
+    LMR_HIP(launch_mi_bwd(F, c->img, c->Mw, c->graw, c->g, c->p.mi_bins, c->mi_map, c->mi_tab,
+                          c->st, c->graw, s));
+    LMR_HIP(launch_smooth(c->graw, c->g, c->p, nullptr, c->G, s));
+  } else {
+    LMR_HIP(launch_demons_keep(F, c->img, c->Mw, c->graw, c->g, nullptr, c->maps, s));
+  }
+  if (c->H) LMR_HIP(launch_tile_hessian(c->G, c->g, c->p.tile, c->H, nullptr, 0, s));
+  if (c->am) {
+    LMR_HIP(launch_fill(c->am, 3 * c->g.N, 0.0f, s));
+    LMR_HIP(launch_fill(c->av, 3 * c->g.N, 0.0f, s));
+  }
   c->begun = true;
   return LMR_OK;
 }
@@ -215,8 +355,15 @@ lmr_status lmr_begin(lmr_ctx* c, const void* F, const void* M, const float* fiel
 // The statistics of F are kept from lmr_begin; a step given another fixed
 // image buffer recomputes them first (an image rewritten in place is the
 // caller's to avoid, as documented).
-static lmr_status refresh_fstat(lmr_ctx* c, const void* F) {
-  if (F == c->fstat_of) return LMR_OK;
+static lmr_status refresh_fstat(lmr_ctx* c, const void* F, const void* M) {
+  if (c->p.similarity == LMR_SIM_MI && (F != c->mi_of[0] || M != c->mi_of[1])) {
+    LMR_HIP(launch_mi_range(F, M, c->img, c->g, c->p.mi_bins, c->mi_rpart, c->mi_map,
+                            c->stream));
+    c->mi_of[0] = F;
+    c->mi_of[1] = M;
+    return LMR_OK;
+  }
+  if (F == c->fstat_of || c->p.similarity != LMR_SIM_LNCC) return LMR_OK;
   LMR_HIP(launch_fstat(F, c->img, c->g, c->p, c->fstat, c->stream));
   c->fstat_of = F;
   return LMR_OK;
@@ -226,7 +373,7 @@ lmr_status lmr_step(lmr_ctx* c, const void* F, const void* M, int n) {
   if (!c || !F || !M || n < 0) return LMR_EINVAL;
   if (!c->begun) return LMR_ESTATE;
   if (n > 0) {
-    const lmr_status r = refresh_fstat(c, F);
+    const lmr_status r = refresh_fstat(c, F, M);
     if (r != LMR_OK) return r;
   }
   for (int i = 0; i < n; ++i) {
@@ -239,9 +386,12 @@ lmr_status lmr_step(lmr_ctx* c, const void* F, const void* M, int n) {
 lmr_status lmr_step_forced(lmr_ctx* c, const void* F, const void* M,
                            const int* decisions, int n) {
   if (!c || !F || !M || n < 0 || (n > 0 && !decisions)) return LMR_EINVAL;
+  if (c->p.optimizer == LMR_OPT_ADAM)
+    for (int i = 0; i < n; ++i)
+      if (decisions[i] == 0) return LMR_EINVAL;
   if (!c->begun) return LMR_ESTATE;
   if (n > 0) {
-    const lmr_status r = refresh_fstat(c, F);
+    const lmr_status r = refresh_fstat(c, F, M);
     if (r != LMR_OK) return r;
   }
   for (int i = 0; i < n; ++i) {
@@ -249,6 +399,12 @@ lmr_status lmr_step_forced(lmr_ctx* c, const void* F, const void* M,
     lmr_status r = enqueue_attempt(c, F, M, d);
     if (r != LMR_OK) return r;
   }
+  return LMR_OK;
+}
+
+lmr_status lmr_workspace_bytes(const lmr_ctx* c, size_t* out) {
+  if (!c || !out) return LMR_EINVAL;
+  *out = c->arena_bytes;
   return LMR_OK;
 }
 
@@ -286,7 +442,7 @@ lmr_status lmr_get_state(lmr_ctx* c, lmr_pair_state* out) {
 }
 
 lmr_status lmr_set_state(lmr_ctx* c, const lmr_pair_state* in) {
-  if (!c || !in) return LMR_EINVAL;
+  if (!c || !in || c->p.optimizer == LMR_OPT_ADAM) return LMR_EINVAL;
   if (!c->begun) return LMR_ESTATE;
   if (!(in->lambda > 0.0) || in->n_hist < 1 || in->retries < 0) return LMR_EINVAL;
   DevState v{};
@@ -294,7 +450,7 @@ lmr_status lmr_set_state(lmr_ctx* c, const lmr_pair_state* in) {
   v.loss = in->loss;
   v.loss_prev = in->loss_prev;
   v.cand_loss = in->cand_loss;
-  v.r = 1.0 + in->loss;
+  v.r = residual_of(in->loss, c->p.similarity, c->p.mi_bins);
   v.n_hist = in->n_hist;
   v.retries = in->retries;
   v.accepted = in->accepted;
@@ -309,18 +465,40 @@ lmr_status lmr_loss_grad(lmr_ctx* c, const void* F, const void* M, const float* 
                          float* cc_map) {
   if (!c || !F || !M || !u) return LMR_EINVAL;
   hipStream_t s = c->stream;
-  // a stage call may pass any fixed image: its statistics are taken here
-  LMR_HIP(launch_fstat(F, c->img, c->g, c->p, c->fstat, s));
-  c->fstat_of = F;
-  LMR_HIP(launch_warp(M, c->img, u, c->g, c->Mw, nullptr, s));
-  LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, nullptr, c->maps,
-                     c->partials, cc_map, s));
-  LMR_HIP(launch_decide(c->st, c->partials, c->nparts, c->g.N, c->dp, 2, -1, 0.0,
-                        c->probe, s));
+  if (c->p.similarity == LMR_SIM_LNCC) {
+    // a stage call may pass any fixed image: its statistics are taken here
+    LMR_HIP(launch_fstat(F, c->img, c->g, c->p, c->fstat, s));
+    c->fstat_of = F;
+    LMR_HIP(launch_warp(M, c->img, u, c->g, c->Mw, nullptr, s));
+    LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, nullptr, c->maps,
+                       c->partials, cc_map, s));
+  } else if (c->p.similarity == LMR_SIM_MI) {
+    if (cc_map) return LMR_EINVAL;
+    LMR_HIP(launch_mi_range(F, M, c->img, c->g, c->p.mi_bins, c->mi_rpart, c->mi_map, s));
+    c->mi_of[0] = F;
+    c->mi_of[1] = M;
+    LMR_HIP(launch_warp(M, c->img, u, c->g, c->Mw, c->graw, s));
+    LMR_HIP(launch_mi_fwd(F, c->img, c->Mw, c->g, c->p.mi_bins, c->mi_map, c->mi_hpart,
+                          c->mi_p, c->mi_tab, c->partials, nullptr, s));
+  } else {
+    // squared error (cc_map receives the squared errors)
+    LMR_HIP(launch_warp(M, c->img, u, c->g, c->Mw, c->graw, s));
+    LMR_HIP(launch_mse_fwd(F, c->img, c->Mw, c->g, c->nparts, c->partials, cc_map, nullptr,
+                           s));
+  }
+  LMR_HIP(launch_decide(c->st, c->partials,
+                        c->p.similarity == LMR_SIM_MI ? 1 : c->nparts, c->g.N, c->dp, 2, -1,
+                        0.0, c->probe, s));
   if (g_raw || g_smooth) {
     float* gr = g_raw ? g_raw : c->graw;
-    LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, nullptr, nullptr,
-                       nullptr, u, nullptr, gr, s));
+    if (c->p.similarity == LMR_SIM_LNCC)
+      LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, nullptr, nullptr,
+                         nullptr, u, nullptr, gr, s));
+    else if (c->p.similarity == LMR_SIM_MI)
+      LMR_HIP(launch_mi_bwd(F, c->img, c->Mw, c->graw, c->g, c->p.mi_bins, c->mi_map,
+                            c->mi_tab, nullptr, gr, s));
+    else
+      LMR_HIP(launch_mse_bwd(F, c->img, c->Mw, c->graw, c->g, nullptr, c->probe, gr, s));
     if (g_smooth) LMR_HIP(launch_smooth(gr, c->g, c->p, nullptr, g_smooth, s));
   }
   double L = 0.0;
@@ -333,8 +511,14 @@ lmr_status lmr_loss_grad(lmr_ctx* c, const void* F, const void* M, const float* 
 lmr_status lmr_update(lmr_ctx* c, const float* u, const float* g_smooth, double r,
                       double lambda, float* u_out) {
   if (!c || !u || !g_smooth || !u_out || u == u_out) return LMR_EINVAL;
+  if (c->p.optimizer == LMR_OPT_ADAM || c->p.similarity == LMR_SIM_DEMONS) return LMR_EINVAL;
+  StepExtra ex = c->extra();
+  if (ex.mode == 1) {
+    LMR_HIP(launch_tile_hessian(g_smooth, c->g, c->p.tile, c->H, nullptr, 0, c->stream));
+    ex.H = c->H;
+  }
   LMR_HIP(launch_update(nullptr, LMR_F32, c->g, c->p, nullptr, g_smooth, nullptr,
-                        nullptr, u, u_out, r, lambda, c->Mw, nullptr, c->stream));
+                        nullptr, u, u_out, r, lambda, c->Mw, nullptr, c->stream, &ex));
   return LMR_OK;
 }
 
@@ -369,7 +553,7 @@ lmr_status lmr_decide_probe(lmr_ctx* c, const lmr_pair_state* in, double cand_lo
   h.loss = in->loss;
   h.loss_prev = in->loss_prev;
   h.cand_loss = in->cand_loss;
-  h.r = 1.0 + in->loss;
+  h.r = residual_of(in->loss, c->p.similarity, c->p.mi_bins);
   h.n_hist = in->n_hist;
   h.retries = in->retries;
   h.accepted = in->accepted;

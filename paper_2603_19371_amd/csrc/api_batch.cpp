@@ -124,6 +124,9 @@ lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes, lmr_
   if (!out || npairs < 1 || npairs > 4096 || !shapes) return LMR_EINVAL;
   *out = nullptr;
   if (!params_ok(p) || (img != LMR_F32 && img != LMR_BF16)) return LMR_EINVAL;
+  // the batched kernel runs the rank-1 LM attempt only
+  if (p->tile != 1 || p->optimizer != LMR_OPT_LM || p->similarity != LMR_SIM_LNCC)
+    return LMR_EINVAL;
   const int rb = p->window / 2, rg = gauss_r(p->grad_sigma);
   const void* kernel = batch_kernel(img, static_cast<lmr_accum>(p->accum), rb, rg);
   if (!kernel) return LMR_EINVAL;  // Gaussian radius beyond the instantiated range

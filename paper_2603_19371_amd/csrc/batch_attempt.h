@@ -127,7 +127,8 @@ __global__ void __launch_bounds__(kNT)
     const int z0 = (local / (tx * ty)) * P.ucz;
     const int z1 = min(z0 + P.ucz, P.g.nz);
     if (P.compositive) {
-      staged_update_tile(static_cast<const T*>(P.M), P.g, a, bx, by, z0, z1, lds.upd);
+      staged_update_tile(static_cast<const T*>(P.M), P.g, a, point_step(a, P.g), bx, by, z0,
+                         z1, lds.upd);
     } else {
       const int x = bx + static_cast<int>(threadIdx.x) % kSX;
       const int y = by + static_cast<int>(threadIdx.x) / kSX;

@@ -40,6 +40,21 @@ struct lmr_ctx {
   double* part_probe;
   unsigned long long* counter;
   bool begun;
+  size_t arena_bytes;  // the whole workspace (lmr_workspace_bytes)
+  // tile_size > 1 (eq. tilen): mean g g^T per tile [tiles][6]
+  double* H;
+  int tiles[3];  // tiles along x, y, z
+  // Adam comparator: first and second moments [3][N] each
+  float* am;
+  float* av;
+  // mutual information: partial histograms, p, gradient table, bin maps
+  unsigned long long* mi_hpart;
+  double* mi_p;
+  double* mi_tab;
+  double* mi_map;
+  float* mi_rpart;
+  const void* mi_of[2];  // the images the bin maps were taken from
+  lmr::StepExtra extra() const;
 };
 
 namespace lmr {

@@ -65,13 +65,15 @@ __device__ void decide_block(DevState* st, const double* __restrict__ partials,
       st->loss = L;
       st->loss_prev = L;
       st->cand_loss = L;
-      st->r = 1.0 + L;
+      st->r = residual_of(L, dp.similarity, dp.mi_bins);
       st->n_hist = 1;
       st->retries = 0;
       st->accepted = 1;
       st->stalled = 0;
       st->cur = 0;
       st->attempts = 0;
+      st->adam_pow1 = dp.adam_beta1;
+      st->adam_pow2 = dp.adam_beta2;
     } else {
       // the decision on the state read at entry; the new state is written back
       DevState n = cur_st;
@@ -93,7 +95,7 @@ __device__ void decide_block(DevState* st, const double* __restrict__ partials,
         n.lambda = clamp_d(f * n.lambda, dp.lambda_min, dp.lambda_max);
         n.loss_prev = n.loss;
         n.loss = L;
-        n.r = 1.0 + L;
+        n.r = residual_of(L, dp.similarity, dp.mi_bins);
         n.n_hist += 1;
         n.retries = 0;
         n.cur = 1 - n.cur;
@@ -103,6 +105,9 @@ __device__ void decide_block(DevState* st, const double* __restrict__ partials,
         if (n.retries >= dp.max_retries && n.lambda >= dp.lambda_max) n.stalled = 1;
       }
       n.accepted = acc;
+      // beta^t of the step that follows (t = attempts + 1)
+      n.adam_pow1 *= dp.adam_beta1;
+      n.adam_pow2 *= dp.adam_beta2;
       *st = n;
     }
   }

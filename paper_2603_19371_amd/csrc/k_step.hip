@@ -50,57 +50,115 @@ __global__ void __launch_bounds__(kBX* kBY)
   }
 }
 
-template <typename T>
+// The step policy of mode MODE (0 eq. tile1, 1 eq. tilen, 2 Adam, 3 a given
+// direction field: the smoothed Demons step) for the
+// update arguments a; r and lambda in FP64 (state or explicit arguments).
+template <int MODE>
+struct StepOf;
+template <>
+struct StepOf<0> {
+  using type = PointStep;
+  __device__ static PointStep make(const UpdateArgs& a, const Geom& g, const StepExtra&,
+                                   const DevState*, double, double) {
+    return point_step(a, g);
+  }
+};
+template <>
+struct StepOf<1> {
+  using type = TileStep;
+  __device__ static TileStep make(const UpdateArgs& a, const Geom& g, const StepExtra& x,
+                                  const DevState*, double r, double lam) {
+    return TileStep{a.G, x.H, static_cast<int>(g.N), x.k, x.tx, x.ty, r, lam, a.eps};
+  }
+};
+template <>
+struct StepOf<2> {
+  using type = AdamStep;
+  __device__ static AdamStep make(const UpdateArgs& a, const Geom& g, const StepExtra& x,
+                                  const DevState* st, double, double) {
+    return AdamStep{a.G,
+                    x.m,
+                    x.v,
+                    static_cast<int>(g.N),
+                    x.b1,
+                    x.ob1,
+                    x.b2,
+                    x.ob2,
+                    static_cast<float>(1.0 - st->adam_pow1),
+                    static_cast<float>(1.0 - st->adam_pow2),
+                    x.lr,
+                    x.aeps,
+                    a.eps};
+  }
+};
+
+template <>
+struct StepOf<3> {
+  using type = GivenStep;
+  __device__ static GivenStep make(const UpdateArgs& a, const Geom& g, const StepExtra&,
+                                   const DevState*, double, double) {
+    return GivenStep{a.G, static_cast<int>(g.N), a.eps};
+  }
+};
+
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kBX* kBY)
     k_update(const T* __restrict__ M, Geom g, const DevState* __restrict__ st,
              const float* __restrict__ G, float* U0, float* U1,
-             const float* u_in, float* u_out, float r_arg, float lam_arg,
-             float eps, int compositive, float* __restrict__ Mw, float* dMw) {
+             const float* u_in, float* u_out, double r_arg, double lam_arg,
+             float eps, int compositive, float* __restrict__ Mw, float* dMw, StepExtra ex) {
   UpdateArgs a;
+  double r = r_arg, lam = lam_arg;
   if (st) {
     if (st->stalled) return;
     a = update_args_from_state(st, U0, U1, G, Mw, eps, compositive);
     a.dMw = dMw;
+    r = st->r;
+    lam = st->lambda;
   } else {
     a.uin = u_in;
     a.uo = u_out;
     a.G = G;
     a.Mw = Mw;
     a.dMw = nullptr;
-    a.r = r_arg;
-    a.lam = lam_arg;
+    a.r = static_cast<float>(r_arg);
+    a.lam = static_cast<float>(lam_arg);
     a.eps = eps;
     a.compositive = compositive;
   }
   const int x = blockIdx.x * kBX + threadIdx.x;
   const int y = blockIdx.y * kBY + threadIdx.y;
   if (x >= g.nx || y >= g.ny) return;
-  update_voxels<T, kUpdZ>(M, g, a, x, y, blockIdx.z * kUpdZ);
+  const auto step = StepOf<MODE>::make(a, g, ex, st, r, lam);
+  update_voxels<T, kUpdZ>(M, g, a, step, x, y, blockIdx.z * kUpdZ);
 }
 
 // The update with the accepted field staged in LDS (staged_update_tile),
 // one tile per block.
 constexpr int kStagedMinBlocks = 1024, kStagedBlocks = 1024;
 
-template <typename T>
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kSNT)
     k_update_staged(const T* __restrict__ M, Geom g, const DevState* __restrict__ st,
                     const float* __restrict__ G, float* U0, float* U1, const float* u_in,
-                    float* u_out, float r_arg, float lam_arg, float eps,
-                    float* __restrict__ Mw, float* dMw, int cz) {
+                    float* u_out, double r_arg, double lam_arg, float eps,
+                    float* __restrict__ Mw, float* dMw, int cz, StepExtra ex) {
   UpdateArgs a;
+  double r = r_arg, lam = lam_arg;
   if (st) {
     if (st->stalled) return;
     a = update_args_from_state(st, U0, U1, G, Mw, eps, 1);
     a.dMw = dMw;
+    r = st->r;
+    lam = st->lambda;
   } else {
     a.uin = u_in;
     a.uo = u_out;
     a.G = G;
     a.Mw = Mw;
     a.dMw = nullptr;
-    a.r = r_arg;
-    a.lam = lam_arg;
+    a.r = static_cast<float>(r_arg);
+    a.lam = static_cast<float>(lam_arg);
     a.eps = eps;
     a.compositive = 1;
   }
@@ -110,7 +168,39 @@ __global__ void __launch_bounds__(kSNT)
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int bx = (tile % tiles_x) * kSX, by = ((tile / tiles_x) % tiles_y) * kSY;
   const int z0 = (tile / (tiles_x * tiles_y)) * cz, z1 = min(z0 + cz, g.nz);
-  staged_update_tile(M, g, a, bx, by, z0, z1);
+  staged_update_tile(M, g, a, StepOf<MODE>::make(a, g, ex, st, r, lam), bx, by, z0, z1);
+}
+
+// Mean of g g^T over each tile of side k, accumulated in FP64 in the order
+// z, y, x of the tile's voxels; one thread per tile.
+__global__ void __launch_bounds__(256)
+    k_tile_hessian(const float* __restrict__ G, Geom g, int k, int tx, int ty, int ntiles,
+                   double* __restrict__ H, const DevState* __restrict__ st, int need) {
+  if (st && need) {
+    if (st->stalled) return;
+    if (need == 2 && !st->accepted) return;
+  }
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  const int N = static_cast<int>(g.N);
+  const int bx = t % tx, by = (t / tx) % ty, bz = t / (tx * ty);
+  double h[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int cnt = 0;
+  for (int z = bz * k; z < min(bz * k + k, g.nz); ++z)
+    for (int y = by * k; y < min(by * k + k, g.ny); ++y)
+      for (int x = bx * k; x < min(bx * k + k, g.nx); ++x) {
+        const int i = (z * g.ny + y) * g.nx + x;
+        const double a = G[i], b = G[N + i], c = G[2 * N + i];
+        h[0] += a * a;
+        h[1] += b * b;
+        h[2] += c * c;
+        h[3] += a * b;
+        h[4] += a * c;
+        h[5] += b * c;
+        ++cnt;
+      }
+#pragma unroll
+  for (int e = 0; e < 6; ++e) H[6LL * t + e] = h[e] / cnt;
 }
 
 constexpr int kDecideThreads = 256;
@@ -210,12 +300,14 @@ int staged_cz(int cols, int nz) {
 
 }  // namespace
 
-hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
-                         const lmr_params& p, const DevState* st, const float* G,
-                         float* U0, float* U1, const float* u_in, float* u_out,
-                         double r, double lambda, float* Mw, float* dMw, hipStream_t s) {
+namespace {
+
+template <int MODE>
+hipError_t update_mode(const void* M, lmr_dtype t, const Geom& g, const lmr_params& p,
+                       const DevState* st, const float* G, float* U0, float* U1,
+                       const float* u_in, float* u_out, double r, double lambda, float* Mw,
+                       float* dMw, hipStream_t s, const StepExtra& ex) {
   dim3 blk(kBX, kBY);
-  const float rf = static_cast<float>(r), lf = static_cast<float>(lambda);
   const float eps = static_cast<float>(p.step_eps);
   if (p.compositive) {
     // staged form when the volume gives enough z-chunks of at least 8 planes
@@ -225,25 +317,57 @@ hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
       const int cz = staged_cz(cols, g.nz);
       const dim3 sgrid(cols * ((g.nz + cz - 1) / cz));
       if (t == LMR_BF16)
-        hipLaunchKernelGGL(k_update_staged<uint16_t>, sgrid, dim3(kSNT), 0, s,
+        hipLaunchKernelGGL((k_update_staged<uint16_t, MODE>), sgrid, dim3(kSNT), 0, s,
                            static_cast<const uint16_t*>(M), g, st, G, U0, U1, u_in, u_out,
-                           rf, lf, eps, Mw, dMw, cz);
+                           r, lambda, eps, Mw, dMw, cz, ex);
       else
-        hipLaunchKernelGGL(k_update_staged<float>, sgrid, dim3(kSNT), 0, s,
-                           static_cast<const float*>(M), g, st, G, U0, U1, u_in, u_out, rf,
-                           lf, eps, Mw, dMw, cz);
+        hipLaunchKernelGGL((k_update_staged<float, MODE>), sgrid, dim3(kSNT), 0, s,
+                           static_cast<const float*>(M), g, st, G, U0, U1, u_in, u_out, r,
+                           lambda, eps, Mw, dMw, cz, ex);
       return hipGetLastError();
     }
   }
   const dim3 grid((g.nx + kBX - 1) / kBX, (g.ny + kBY - 1) / kBY, (g.nz + kUpdZ - 1) / kUpdZ);
   if (t == LMR_BF16)
-    hipLaunchKernelGGL(k_update<uint16_t>, grid, blk, 0, s,
+    hipLaunchKernelGGL((k_update<uint16_t, MODE>), grid, blk, 0, s,
                        static_cast<const uint16_t*>(M), g, st, G, U0, U1, u_in, u_out,
-                       rf, lf, eps, p.compositive, Mw, dMw);
+                       r, lambda, eps, p.compositive, Mw, dMw, ex);
   else
-    hipLaunchKernelGGL(k_update<float>, grid, blk, 0, s,
-                       static_cast<const float*>(M), g, st, G, U0, U1, u_in, u_out, rf,
-                       lf, eps, p.compositive, Mw, dMw);
+    hipLaunchKernelGGL((k_update<float, MODE>), grid, blk, 0, s,
+                       static_cast<const float*>(M), g, st, G, U0, U1, u_in, u_out, r,
+                       lambda, eps, p.compositive, Mw, dMw, ex);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
+                         const lmr_params& p, const DevState* st, const float* G,
+                         float* U0, float* U1, const float* u_in, float* u_out,
+                         double r, double lambda, float* Mw, float* dMw, hipStream_t s,
+                         const StepExtra* extra) {
+  const StepExtra ex = extra ? *extra : StepExtra{};
+  switch (ex.mode) {
+    case 0:
+      return update_mode<0>(M, t, g, p, st, G, U0, U1, u_in, u_out, r, lambda, Mw, dMw, s, ex);
+    case 1:
+      return update_mode<1>(M, t, g, p, st, G, U0, U1, u_in, u_out, r, lambda, Mw, dMw, s, ex);
+    case 2:
+      if (!st) return hipErrorInvalidValue;  // the moments' step count lives in the state
+      return update_mode<2>(M, t, g, p, st, G, U0, U1, u_in, u_out, r, lambda, Mw, dMw, s, ex);
+    case 3:
+      return update_mode<3>(M, t, g, p, st, G, U0, U1, u_in, u_out, r, lambda, Mw, dMw, s, ex);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_tile_hessian(const float* G, const Geom& g, int k, double* H,
+                               const DevState* st, int need, hipStream_t s) {
+  const int tx = (g.nx + k - 1) / k, ty = (g.ny + k - 1) / k, tz = (g.nz + k - 1) / k;
+  const int n = tx * ty * tz;
+  hipLaunchKernelGGL(k_tile_hessian, dim3((n + 255) / 256), dim3(256), 0, s, G, g, k, tx, ty,
+                     n, H, st, need);
   return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 #include "lmreg.h"
@@ -24,12 +25,41 @@ struct DevState {
   int32_t cur;       // index (0/1) of the field buffer holding the accepted field
   int32_t pad_;
   int64_t attempts;
+  double adam_pow1;  // beta1^t and beta2^t of the next Adam step t (its bias
+  double adam_pow2;  // corrections are 1 - beta^t)
 };
 
 // Scalars of the decision rule (eq. lambda-update, eq. rejection).
 struct DecideParams {
   double lambda_inc, lambda_dec, lambda_min, lambda_max, tau;
   int max_retries;
+  double adam_beta1, adam_beta2;  // for the bias corrections kept in the state
+  int similarity;                 // lmr_similarity: how the residual r follows from L
+  int mi_bins;                    // B of the mutual information
+};
+
+// The scalar residual of the least-squares form of the loss (Sec. 2.2):
+// r = 1 - LNCC = 1 + L for LNCC (L = -LNCC), r = log2 B - MI = log2 B + L
+// for mutual information (L = -MI), r = sqrt(MSE) for the squared error
+// (its square is the loss).
+__host__ __device__ inline double residual_of(double L, int similarity, int bins) {
+  if (similarity == LMR_SIM_LNCC) return 1.0 + L;
+  if (similarity == LMR_SIM_MI) return log2(static_cast<double>(bins)) + L;
+  return sqrt(L > 0.0 ? L : 0.0);
+}
+
+
+
+// Direction of the update besides eq. tile1 (lmr_params.tile, .optimizer).
+struct StepExtra {
+  int mode;                 // 0 eq. tile1, 1 eq. tilen (pooled Hessian), 2 Adam,
+                            // 3 a given direction (the smoothed Demons step, in G)
+  const double* H;          // mode 1: mean g g^T per tile [tiles][6]
+  int k, tx, ty;            // mode 1: tile side, tiles along x and y
+  float* m;                 // mode 2: moments [3][N] each
+  float* v;
+  float b1, ob1, b2, ob2;   // mode 2: decays and 1 - decays
+  float lr, aeps;           // mode 2: step length, epsilon
 };
 
 struct Geom {
@@ -360,7 +390,50 @@ hipError_t launch_update(const void* M, lmr_dtype t, const Geom& g,
                          const lmr_params& p, const DevState* st,
                          const float* G, float* U0, float* U1, const float* u_in,
                          float* u_out, double r, double lambda, float* Mw, float* dMw,
-                         hipStream_t s);
+                         hipStream_t s, const StepExtra* extra = nullptr);
+// Mutual information (k_mi.hip).  Histogram blocks of the forward pass:
+// kMiBlocks at most (mi_hist_blocks(N)); their partial histograms take
+// kMiBlocks * bins^2 unsigned 64-bit counts.
+constexpr int kMiBlocks = 256;
+int mi_hist_blocks(long long N);
+// map[0..3] = (lo_F, s_F, lo_M, s_M) of the bin coordinates, from the
+// ranges of F and M (part: 4 * kMiBlocks floats of scratch).
+hipError_t launch_mi_range(const void* F, const void* M, lmr_dtype t, const Geom& g, int bins,
+                           float* part, double* map, hipStream_t s);
+// Joint histogram of F and Mw, p (FP64 [bins^2]), the gradient table tab
+// (FP64 [bins^2]) and partials[0] = N MI; a frozen pair is skipped.
+hipError_t launch_mi_fwd(const void* F, lmr_dtype t, const float* Mw, const Geom& g, int bins,
+                         const double* map, unsigned long long* hpart, double* p, double* tab,
+                         double* partials, const DevState* st, hipStream_t s);
+// g = N dr/du from tab (only after an acceptance with a state); dMw may
+// alias graw.
+hipError_t launch_mi_bwd(const void* F, lmr_dtype t, const float* Mw, const float* dMw,
+                         const Geom& g, int bins, const double* map, const double* tab,
+                         const DevState* st, float* graw, hipStream_t s);
+// Squared-error similarity (k_mse.hip).  mse_fwd: one FP64 partial of
+// -sum (F - Mw)^2 per block, nparts blocks (sq_map, may be null: the squared
+// errors); a frozen pair is skipped.  mse_bwd: g = (Mw - F) dMw / r with r
+// the state's residual (only after an acceptance) or sqrt(*loss) without a
+// state; dMw may alias graw.
+hipError_t launch_mse_fwd(const void* F, lmr_dtype t, const float* Mw, const Geom& g,
+                          int nparts, double* partials, float* sq_map, const DevState* st,
+                          hipStream_t s);
+hipError_t launch_mse_bwd(const void* F, lmr_dtype t, const float* Mw, const float* dMw,
+                          const Geom& g, const DevState* st, const double* loss, float* graw,
+                          hipStream_t s);
+// Demons step (eq. demons): du = r_x n_x / (|n_x|^2 + lambda) from keep =
+// [r_x | n_x] ([4][N]) of the accepted field; keep is refreshed by
+// demons_keep after an acceptance (always without a state).
+hipError_t launch_demons_force(const float* keep, const Geom& g, const DevState* st,
+                               float* du, hipStream_t s);
+hipError_t launch_demons_keep(const void* F, lmr_dtype t, const float* Mw, const float* dMw,
+                              const Geom& g, const DevState* st, float* keep,
+                              hipStream_t s);
+// Mean of g g^T over every tile of side k (eq. tilen) into H [tiles][6];
+// need = 2 with a state: only after an acceptance (the gradient changed).
+hipError_t launch_tile_hessian(const float* G, const Geom& g, int k, double* H,
+                               const DevState* st, int need, hipStream_t s);
+
 // Window mean and variance of F (FP64, [2][N]), read by every P2 on that F.
 hipError_t launch_fstat(const void* F, lmr_dtype t, const Geom& g, const lmr_params& p,
                         double* fstat, hipStream_t s);

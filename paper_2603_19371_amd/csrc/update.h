@@ -19,6 +19,114 @@ struct UpdateArgs {
   int compositive;
 };
 
+// ----------------------------------------------------------- step policies
+// The direction e = eps du of one voxel from the accepted state.  A policy
+// loads its per-voxel operands (load: element index i, kFarIndex reads 0)
+// ahead of their use and forms the direction (apply).
+//   PointStep  du = -r g / (|g|^2 + lambda)                   (eq. tile1)
+//   TileStep   du = -r (H_tile + lambda I)^-1 g               (eq. tilen)
+//   AdamStep   du = -lr mhat / (sqrt(vhat) + eps_a), the moments of g
+//              updated in place (the Adam comparator)
+struct PointStep {
+  const float* G;  // smoothed gradient of the accepted field [3][N]
+  int N;
+  float r, lam, eps;
+  struct Regs {
+    float g[3];
+  };
+  __device__ void load(unsigned i, Regs& q) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q.g[c] = bld<float>(make_rbuf_n(G + c * N, N), i);
+  }
+  __device__ void apply(const Regs& q, int, int, int, int, float e[3]) const {
+    const float g0 = q.g[0], g1 = q.g[1], g2 = q.g[2];
+    const float s = -r / fmaf(g2, g2, fmaf(g1, g1, fmaf(g0, g0, lam)));
+    e[0] = eps * (s * g0);
+    e[1] = eps * (s * g1);
+    e[2] = eps * (s * g2);
+  }
+};
+
+// Pooled Hessian of the voxel's tile (side k, tiles from the origin, x
+// fastest; H holds the mean of g g^T over the tile as xx, yy, zz, xy, xz, yz
+// in FP64).  The symmetric 3x3 system is solved by its adjugate in FP64;
+// H + lambda I is positive definite for lambda > 0.
+struct TileStep {
+  const float* G;
+  const double* H;
+  int N, k, tx, ty;
+  double r, lam;
+  float eps;
+  using Regs = PointStep::Regs;
+  __device__ void load(unsigned i, Regs& q) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q.g[c] = bld<float>(make_rbuf_n(G + c * N, N), i);
+  }
+  __device__ void apply(const Regs& q, int, int x, int y, int z, float e[3]) const {
+    const double* h = H + 6 * (((z / k) * ty + y / k) * tx + x / k);
+    const double a = h[0] + lam, b = h[1] + lam, c = h[2] + lam;
+    const double d = h[3], f = h[4], o = h[5];  // xy, xz, yz
+    const double c00 = b * c - o * o, c01 = f * o - d * c, c02 = d * o - b * f;
+    const double c11 = a * c - f * f, c12 = d * f - a * o, c22 = a * b - d * d;
+    const double det = a * c00 + d * c01 + f * c02;
+    const double s = -r / det;
+    const double g0 = q.g[0], g1 = q.g[1], g2 = q.g[2];
+    e[0] = eps * static_cast<float>(s * (c00 * g0 + c01 * g1 + c02 * g2));
+    e[1] = eps * static_cast<float>(s * (c01 * g0 + c11 * g1 + c12 * g2));
+    e[2] = eps * static_cast<float>(s * (c02 * g0 + c12 * g1 + c22 * g2));
+  }
+};
+
+// Adam on the smoothed gradient: m <- b1 m + (1 - b1) g, v <- b2 v +
+// (1 - b2) g^2, du = -lr (m / c1) / (sqrt(v / c2) + eps_a) with the bias
+// corrections c1 = 1 - b1^t, c2 = 1 - b2^t of step t.
+struct AdamStep {
+  const float* G;
+  float* m;  // first moments [3][N], updated in place
+  float* v;  // second moments [3][N], updated in place
+  int N;
+  float b1, ob1, b2, ob2, c1, c2, lr, aeps, eps;  // ob = 1 - b
+  struct Regs {
+    float g[3], m[3], v[3];
+  };
+  __device__ void load(unsigned i, Regs& q) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      q.g[c] = bld<float>(make_rbuf_n(G + c * N, N), i);
+      q.m[c] = bld<float>(make_rbuf_n(m + c * N, N), i);
+      q.v[c] = bld<float>(make_rbuf_n(v + c * N, N), i);
+    }
+  }
+  __device__ void apply(const Regs& q, int i, int, int, int, float e[3]) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float mn = b1 * q.m[c] + ob1 * q.g[c];
+      const float vn = b2 * q.v[c] + ob2 * (q.g[c] * q.g[c]);
+      m[c * N + i] = mn;
+      v[c * N + i] = vn;
+      const float d = -lr * (mn / c1) / (sqrtf(vn / c2) + aeps);
+      e[c] = eps * d;
+    }
+  }
+};
+
+// A given direction field V (the smoothed Demons step, eq. demons): e = eps V.
+struct GivenStep {
+  const float* V;
+  int N;
+  float eps;
+  using Regs = PointStep::Regs;
+  __device__ void load(unsigned i, Regs& q) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q.g[c] = bld<float>(make_rbuf_n(V + c * N, N), i);
+  }
+  __device__ void apply(const Regs& q, int, int, int, int, float e[3]) const {
+    e[0] = eps * q.g[0];
+    e[1] = eps * q.g[1];
+    e[2] = eps * q.g[2];
+  }
+};
+
 template <typename T>
 __device__ __forceinline__ void update_voxel(const T* __restrict__ M, const Geom& g,
                                              const UpdateArgs& a, int x, int y, int z) {
@@ -65,23 +173,25 @@ __device__ __forceinline__ void update_voxel(const T* __restrict__ M, const Geom
 // flight together: the step is bound by the latency of its two dependent
 // gathers, not by bandwidth.  Per voxel the arithmetic is that of
 // update_voxel, bit for bit.
-template <typename T, int V>
+template <typename T, int V, class S>
 __device__ __forceinline__ void update_voxels(const T* __restrict__ M, const Geom& g,
-                                              const UpdateArgs& a, int x, int y, int z0) {
+                                              const UpdateArgs& a, const S& step, int x,
+                                              int y, int z0) {
   const int N = static_cast<int>(g.N);
   int idx[V];
   bool ok[V];
   float e[V][3], n[V][3], mw[V], dm[V][3];
+  typename S::Regs q[V];
 #pragma unroll
   for (int j = 0; j < V; ++j) {
     ok[j] = z0 + j < g.nz;
     idx[j] = ((ok[j] ? z0 + j : z0) * g.ny + y) * g.nx + x;
-    const int i = idx[j];
-    const float g0 = a.G[i], g1 = a.G[N + i], g2 = a.G[2 * N + i];
-    const float s = -a.r / fmaf(g2, g2, fmaf(g1, g1, fmaf(g0, g0, a.lam)));
-    e[j][0] = a.eps * (s * g0);
-    e[j][1] = a.eps * (s * g1);
-    e[j][2] = a.eps * (s * g2);
+    step.load(static_cast<unsigned>(idx[j]), q[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    e[j][0] = e[j][1] = e[j][2] = 0.0f;
+    if (ok[j]) step.apply(q[j], idx[j], x, y, z0 + j, e[j]);
   }
   if (a.compositive) {
     const RBuf b0 = make_rbuf_n(a.uin, N), b1 = make_rbuf_n(a.uin + N, N),
@@ -156,10 +266,11 @@ struct StagedLds {
 
 // One tile of the staged update: voxels [bx, bx+32) x [by, by+8) x [z0, z1)
 // (clipped to the volume), with a block of 256 threads, in the LDS `sm`.
-template <typename T>
+template <typename T, class S>
 __device__ __forceinline__ void staged_update_tile(const T* __restrict__ M, const Geom& g,
-                                                   const UpdateArgs& a, int bx, int by,
-                                                   int z0, int z1, StagedLds& sm) {
+                                                   const UpdateArgs& a, const S& step,
+                                                   int bx, int by, int z0, int z1,
+                                                   StagedLds& sm) {
   auto& s_u = sm.u;
   // a block that runs tiles back to back: every thread is done with the
   // previous tile's slots before they are overwritten
@@ -213,14 +324,11 @@ __device__ __forceinline__ void staged_update_tile(const T* __restrict__ M, cons
   commit(z0);
   fetch(z0 + 1);
   const RBuf bm = make_rbuf_n(M, N);
-  const RBuf bg[3] = {make_rbuf_n(a.G, N), make_rbuf_n(a.G + N, N),
-                      make_rbuf_n(a.G + 2 * N, N)};
-  // the gradient of the next plane is in flight while a plane is processed
+  // the step operands of the next plane are in flight while a plane is
+  // processed
   const unsigned col = own ? static_cast<unsigned>(y * g.nx + x) : kFarIndex;
-  float gn[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-    gn[c] = bld<float>(bg[c], own ? static_cast<unsigned>(z0 * plane) + col : kFarIndex);
+  typename S::Regs qn;
+  step.load(own ? static_cast<unsigned>(z0 * plane) + col : kFarIndex, qn);
   // The image gather M(x + u~) of a plane stays in flight while the next
   // plane's field work runs; it is finished (interpolated and stored) then.
   const bool warp = M && a.Mw;
@@ -242,18 +350,15 @@ __device__ __forceinline__ void staged_update_tile(const T* __restrict__ M, cons
     // barrier of the previous iteration
     commit(z + 1);
     if (z + 2 <= z1) fetch(z + 2);
-    const float g0 = gn[0], g1 = gn[1], g2 = gn[2];
-    if (z + 1 < z1) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        gn[c] = bld<float>(bg[c], own ? static_cast<unsigned>((z + 1) * plane) + col
-                                      : kFarIndex);
-    }
+    const typename S::Regs q = qn;
+    if (z + 1 < z1)
+      step.load(own ? static_cast<unsigned>((z + 1) * plane) + col : kFarIndex, qn);
     __syncthreads();
     if (!own) continue;
     const int i = (z * g.ny + y) * g.nx + x;
-    const float s = -a.r / fmaf(g2, g2, fmaf(g1, g1, fmaf(g0, g0, a.lam)));
-    const float e0 = a.eps * (s * g0), e1 = a.eps * (s * g1), e2 = a.eps * (s * g2);
+    float e[3];
+    step.apply(q, i, x, y, z, e);
+    const float e0 = e[0], e1 = e[1], e2 = e[2];
     const BCell c = make_bcell(g, x, y, z, e0, e1, e2);
     float b[3];
     if (e0 >= -1.0f && e0 < 1.0f && e1 >= -1.0f && e1 < 1.0f && e2 >= -1.0f && e2 < 1.0f) {
@@ -298,12 +403,17 @@ __device__ __forceinline__ void staged_update_tile(const T* __restrict__ M, cons
   if (own) finish();
 }
 
-template <typename T>
+template <typename T, class S>
 __device__ __forceinline__ void staged_update_tile(const T* __restrict__ M, const Geom& g,
-                                                   const UpdateArgs& a, int bx, int by,
-                                                   int z0, int z1) {
+                                                   const UpdateArgs& a, const S& step,
+                                                   int bx, int by, int z0, int z1) {
   __shared__ StagedLds sm;
-  staged_update_tile(M, g, a, bx, by, z0, z1, sm);
+  staged_update_tile(M, g, a, step, bx, by, z0, z1, sm);
+}
+
+// The rank-1 step of the update arguments (eq. tile1).
+__device__ __forceinline__ PointStep point_step(const UpdateArgs& a, const Geom& g) {
+  return PointStep{a.G, static_cast<int>(g.N), a.r, a.lam, a.eps};
 }
 
 // The update arguments of an attempt in state mode: the accepted field is

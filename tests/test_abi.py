@@ -47,7 +47,9 @@ def test_default_params_and_errors_without_device():
     h = C.c_void_p()
     for bad in (dict(window=4), dict(window=11), dict(lambda_inc=1.0),
                 dict(lambda_dec=1.0), dict(grad_sigma=-1.0), dict(step_eps=0.0),
-                dict(lambda_min=0.0), dict(max_retries=0), dict(accum=7)):
+                dict(lambda_min=0.0), dict(max_retries=0), dict(accum=7),
+                dict(tile=0), dict(tile=17), dict(optimizer=2), dict(optimizer=1, tile=2),
+                dict(optimizer=1, adam_lr=0.0), dict(optimizer=1, adam_beta2=1.0)):
         pb = _lib.Params.make(**bad)
         assert L.lmr_create(C.byref(h), 8, 8, 8, 0, C.byref(pb), None) == 1, bad
     assert L.lmr_create(C.byref(h), 0, 8, 8, 0, C.byref(p), None) == 1
