@@ -223,6 +223,28 @@ lmr_status lmr_loss_grad(lmr_ctx* ctx, const void* fixed, const void* moving,
                          const float* u, double* loss_out, float* g_raw,
                          float* g_smooth, float* cc_map);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * results of lmr_loss_grad without a context and without any allocation.
+ * F, M: device images of type img, [nz][ny][nx]; u: device field
+ * [3][nz][ny][nx]; p: the parameters (window, grad_sigma, cc_eps, accum are
+ * used); loss_dev: device double receiving L = -mean cc; g_raw, g_smooth
+ * (device [3][nz][ny][nx], either may be NULL, not the same buffer) and
+ * cc_map (device [nz][ny][nx], may be NULL) as in lmr_loss_grad.  The
+ * results are bitwise those of lmr_loss_grad on the same inputs.
+ * Enqueues on `stream` and returns without synchronising.
+ * Workspace: one static device array of this library (about 48 MiB, held
+ * by every GPU the library runs on until the process ends), so volumes are
+ * limited to nz*ny*nx <= 2^20 voxels; larger ones give LMR_EINVAL.  Every
+ * call on a GPU uses that GPU's one array: calls that overlap on one GPU
+ * (different streams or threads) race and must be serialised by the
+ * caller.  Nothing in it needs clearing between calls (each call writes
+ * every value it reads). */
+lmr_status lmr_loss_grad_noalloc(const void* fixed, const void* moving, lmr_dtype img,
+                                 const float* u, int nz, int ny, int nx,
+                                 const lmr_params* p, double* loss_dev, float* g_raw,
+                                 float* g_smooth, float* cc_map, hipStream_t stream);
+
 /* Test hook: steps 1-2 alone.  u_out = eps du + u o (Id + eps du) with
  * du = -r g / (|g|^2 + lambda) (device arrays, [3][nz][ny][nx]), or with
  * tile > 1 du = -r (H_tile + lambda I)^-1 g, H_tile pooled from g_smooth

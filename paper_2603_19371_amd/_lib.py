@@ -145,6 +145,8 @@ def lib() -> C.CDLL:
             "lmr_unet_adam": (_I, [_V, _D, _D, _D, _D, _D]),
             "lmr_unet_layer_probe": (_I, [_V, _I, _V, _I, _V, _I, _V, _I, _V, _I, _V,
                                           _V]),
+            "lmr_loss_grad_noalloc": (_I, [_V, _V, _I, _V, _I, _I, _I, C.POINTER(Params),
+                                           _V, _V, _V, _V, _V]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -171,7 +173,8 @@ def exported_symbols():
             "lmr_batch_destroy", "lmr_unet_param_count", "lmr_unet_layer_info",
             "lmr_unet_create", "lmr_unet_destroy", "lmr_unet_set_params",
             "lmr_unet_get_params", "lmr_unet_get_grads", "lmr_unet_forward",
-            "lmr_unet_backward", "lmr_unet_adam", "lmr_unet_layer_probe"]
+            "lmr_unet_backward", "lmr_unet_adam", "lmr_unet_layer_probe",
+            "lmr_loss_grad_noalloc"]
 
 
 def _check(status: int, what: str):
@@ -331,6 +334,35 @@ class Context:
                                 self._field(g_smooth, "g_smooth"), float(r),
                                 float(lam), self._field(out, "out")), "lmr_update")
         return out
+
+
+def loss_grad_noalloc(F, M, u, params: Params | None = None, raw=True, smooth=True,
+                      cc=False, out=None, stream=None, **kw):
+    """lmr_loss_grad_noalloc: loss and gradients of u without a context and
+    without allocating in the library.  Returns (loss, g_raw, g_smooth, cc)
+    as device tensors (loss: float64 [1]); `out` may supply them (a dict with
+    keys loss, g_raw, g_smooth, cc) so that the call allocates nothing at
+    all.  Enqueues only."""
+    shape = tuple(F.shape)
+    p = params if params is not None else Params.make(**kw)
+    f = _dev(F, shape, F.dtype, "fixed")
+    m = _dev(M, shape, F.dtype, "moving")
+    up = _dev(u, (3,) + shape, torch.float32, "u")
+    out = dict(out or {})
+    if "loss" not in out:
+        out["loss"] = torch.empty(1, dtype=torch.float64, device="cuda")
+    for key, want, sh in (("g_raw", raw, (3,) + shape), ("g_smooth", smooth, (3,) + shape),
+                          ("cc", cc, shape)):
+        if want and key not in out:
+            out[key] = torch.empty(sh, device="cuda")
+        if not want:
+            out[key] = None
+    ptr = {k: (_dev(v, tuple(v.shape), v.dtype, k) if v is not None else None)
+           for k, v in out.items()}
+    _check(lib().lmr_loss_grad_noalloc(f, m, _img_code(F), up, *shape, C.byref(p),
+                                       ptr["loss"], ptr["g_raw"], ptr["g_smooth"], ptr["cc"],
+                                       _stream_handle(stream)), "lmr_loss_grad_noalloc")
+    return out["loss"], out["g_raw"], out["g_smooth"], out["cc"]
 
 
 def warp(M: torch.Tensor, u: torch.Tensor, with_grad=False, stream=None):
