@@ -219,9 +219,9 @@ lmr_status lmr_unet_create(lmr_unet** out, int nz, int ny, int nx, hipStream_t s
     A(pk, reinterpret_cast<void**>(&u->Wb[l]));
     const int* d = u->dims[kLayers[l].level];
     const long long a = unet_wgrad_part_floats(pad16(kLayers[l].cin),
-                                               pad16(kLayers[l].cout), d[0], d[1]);
+                                               pad16(kLayers[l].cout), d[0], d[1], d[2]);
     const long long b = unet_wgrad_bias_floats(pad16(kLayers[l].cin),
-                                               pad16(kLayers[l].cout), d[0], d[1]);
+                                               pad16(kLayers[l].cout), d[0], d[1], d[2]);
     if (a > part_n) part_n = a;
     if (b > partb_n) partb_n = b;
   }

@@ -30,6 +30,8 @@ namespace {
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
 // FP32 -> BF16, round to nearest even (NaN stays NaN).
 __device__ __forceinline__ uint16_t f2bf(float v) {
@@ -116,171 +118,437 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
 }
 
 // The same convolution with the operands staged in LDS.  A block owns a
-// 16 x 16 (x, y) tile of output voxels in one z plane and 16 output
+// 16 x 16 (x, y) tile of output voxels in one z plane and 16 NT output
 // channels; per chunk of 16 input channels it stages the 3 x 18 x 18 input
 // halo and the chunk's 27 weight slices, then each wave runs the MFMAs of
-// four 16-voxel rows for all 27 taps from LDS, reusing each weight operand
-// across its four rows.  (The streamed form above reads both operands from
+// four 16-voxel rows for all 27 taps from LDS: each weight operand serves
+// the four rows, each input operand the NT output-channel tiles.  Every load
+// of a chunk is issued before the first is used (one memory latency per
+// chunk, not one per load), and the next chunk's loads are in flight while
+// the current chunk's MFMAs run.  Input positions outside the volume, and
+// channels past cin_valid, read 0 through the buffer resource (an offset
+// beyond the tensor).  (The streamed form above reads both operands from
 // memory for every MFMA and is bound by the memory unit's per-instruction
 // cost.)
+//
+// The MFMA computes D[co][voxel] = sum_ci W[co][ci] X[voxel][ci] (weights as
+// the A operand), so that each lane receives four consecutive output channels
+// of one voxel: the epilogue stores them as one 8-byte (BF16) or 16-byte
+// (FP32) write.
+//
+// LDS rows (one voxel, or one weight row: 16 channels) are 40 bytes apart.
+// An operand read takes the same 8-byte quad of 16 consecutive rows; with a
+// 32-byte pitch those fall on 4 bank groups (a 4-way conflict), with 40
+// bytes (10 dwords) 10 m mod 32 covers all 16 even banks.  The pitch keeps
+// every LDS address affine in the tap, so the unrolled taps read at
+// immediate offsets from one base per lane.
+//
+// Staging is arranged so that every address is a per-thread base plus a
+// compile-time or per-block constant: the input halo is 54 rows (3 planes x
+// 18 rows) of 72 items (18 voxels x 4 quads); threads 0..215 each take one
+// item position in rows r0, r0 + 3, ... (r0 = thread / 72), 18 loads.
 constexpr int kCT = 16;            // tile edge (x and y)
 constexpr int kCH = kCT + 2;       // halo tile edge
+constexpr int kPitch = 20;         // LDS row pitch, uint16 elements (40 bytes)
+constexpr int kXLoads = 18;        // halo loads per staging thread
+constexpr int kXThreads = 216;     // staging threads (3 rows x 72 items)
+template <int NT>
 __global__ void __launch_bounds__(256) k_conv_tile(ConvArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t s_x[3][kCH][kCH][16];
-  __shared__ __attribute__((aligned(16))) uint16_t s_w[27][16][16];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int nco = a.cout_p / 16;
+  constexpr int kWRows = 27 * 16 * NT;            // weight rows per chunk
+  constexpr int kWPer = (kWRows * 4 + 255) / 256;  // weight loads per thread
+  constexpr int kTStep = 64 / (16 * NT);           // taps between a thread's loads
+  __shared__ __attribute__((aligned(16))) uint16_t s_x[3 * kCH * kCH * kPitch];
+  __shared__ __attribute__((aligned(16))) uint16_t s_w[kWRows * kPitch];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nco = a.cout_p / (16 * NT);
   const int x0 = blockIdx.x * kCT, y0 = blockIdx.y * kCT;
-  const int z = blockIdx.z / nco, co0 = (blockIdx.z % nco) * 16;
+  const int z = blockIdx.z / nco, co0 = (blockIdx.z % nco) * 16 * NT;
   const int m = lane & 15, kq = lane >> 4;
-  f4 acc[4];
+  const int q = tid & 3;  // the quad (4 channels) this thread stages
+  // ---- input staging: element offsets of this thread's 18 items (chunk 0)
+  const long long nvox = (long long)a.nz * a.ny * a.nx;
+  const RBuf bx = make_rbuf(
+      a.X, static_cast<unsigned>(((nvox - 1) * a.ldx + ((a.cin_valid + 3) & ~3)) * 2));
+  const int r0 = tid / 72, xx = (tid % 72) >> 2;
+  const int gx = x0 + xx - 1;
+  const bool xok = tid < kXThreads && (unsigned)gx < (unsigned)a.nx;
+  const int row_st = a.nx * a.ldx, plane_st = a.ny * row_st;  // elements
+  // item (zz, yi): voxel (gx, y0 + r0 + 3 yi - 1, z + zz - 1)
+  const int xbase = ((z - 1) * a.ny + y0 + r0 - 1) * row_st + gx * a.ldx + 4 * q;
+  unsigned yok = 0;  // bit yi: row y0 + r0 + 3 yi - 1 inside the volume
 #pragma unroll
-  for (int r = 0; r < 4; ++r) acc[r] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int yi = 0; yi < 6; ++yi)
+    yok |= ((unsigned)(y0 + r0 + 3 * yi - 1) < (unsigned)a.ny ? 1u : 0u) << yi;
+  const int sx_base = (r0 * kCH + xx) * kPitch + 4 * q;  // LDS element offset
+  // ---- weight staging: rows R = tid / 4 + 64 j (tap R / 16 NT, channel R % 16 NT)
+  const RBuf bw = make_rbuf(a.W, static_cast<unsigned>(27LL * a.cout_p * a.cin_p * 2));
+  const int wrow = tid >> 2;
+  const int wbase = ((wrow / (16 * NT)) * a.cout_p + co0 + wrow % (16 * NT)) * a.cin_p + 4 * q;
+  const int wstep = kTStep * a.cout_p * a.cin_p;
+  s4 rx[kXLoads], rw[kWPer];
+  auto fetch = [&](int c0) {
+    const bool cok = xok && c0 + 4 * q < a.cin_valid;
+#pragma unroll
+    for (int i = 0; i < kXLoads; ++i) {
+      const int zz = i / 6, yi = i % 6;
+      const bool ok = cok && ((yok >> yi) & 1u) && (unsigned)(z + zz - 1) < (unsigned)a.nz;
+      const int e = xbase + zz * plane_st + 3 * yi * row_st + c0;
+      const unsigned o = ok ? static_cast<unsigned>(e) * 2u : kFarOffset;
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(bx.r, o, 0, 0);
+      rx[i] = s4{static_cast<short>(v[0] & 0xFFFFu), static_cast<short>(v[0] >> 16),
+                 static_cast<short>(v[1] & 0xFFFFu), static_cast<short>(v[1] >> 16)};
+    }
+#pragma unroll
+    for (int j = 0; j < kWPer; ++j) {
+      const unsigned o = wrow + 64 * j < kWRows
+                             ? static_cast<unsigned>(wbase + j * wstep + c0) * 2u
+                             : kFarOffset;
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(bw.r, o, 0, 0);
+      rw[j] = s4{static_cast<short>(v[0] & 0xFFFFu), static_cast<short>(v[0] >> 16),
+                 static_cast<short>(v[1] & 0xFFFFu), static_cast<short>(v[1] >> 16)};
+    }
+  };
+  auto commit = [&]() {
+    if (tid < kXThreads) {
+#pragma unroll
+      for (int i = 0; i < kXLoads; ++i)
+        *reinterpret_cast<s4*>(&s_x[sx_base + i * 3 * kCH * kPitch]) = rx[i];
+    }
+#pragma unroll
+    for (int j = 0; j < kWPer; ++j)
+      if (wrow + 64 * j < kWRows)
+        *reinterpret_cast<s4*>(&s_w[(wrow + 64 * j) * kPitch + 4 * q]) = rw[j];
+  };
+  f4 acc[NT][4];
+#pragma unroll
+  for (int n = 0; n < NT; ++n)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[n][r] = f4{0.f, 0.f, 0.f, 0.f};
+  // operand bases: halo voxel (m, 4 wv) of plane 0, weight row m of tap 0
+  const int xr_base = (4 * wv * kCH + m) * kPitch + 4 * kq;
+  const int wr_base = m * kPitch + 4 * kq;
+  fetch(0);
   for (int c0 = 0; c0 < a.cin_p; c0 += 16) {
     __syncthreads();  // the previous chunk's operands are no longer read
-    // input halo: 3 x 18 x 18 voxels x 16 channels, 4 channels per item
-    for (int it = threadIdx.x; it < 3 * kCH * kCH * 4; it += 256) {
-      const int q = it & 3, p = it >> 2;
-      const int xx = p % kCH, yy = (p / kCH) % kCH, zz = p / (kCH * kCH);
-      const int gx = x0 + xx - 1, gy = y0 + yy - 1, gz = z + zz - 1;
-      const int ci = c0 + 4 * q;
-      s4 v = {0, 0, 0, 0};
-      if ((unsigned)gx < (unsigned)a.nx && (unsigned)gy < (unsigned)a.ny &&
-          (unsigned)gz < (unsigned)a.nz && ci < a.cin_valid)
-        v = *reinterpret_cast<const s4*>(
-            a.X + ((long long)(gz * a.ny + gy) * a.nx + gx) * a.ldx + ci);
-      *reinterpret_cast<s4*>(&s_x[zz][yy][xx][4 * q]) = v;
-    }
-    // weights of the chunk: 27 taps x 16 output x 16 input channels
-    for (int it = threadIdx.x; it < 27 * 16 * 4; it += 256) {
-      const int q = it & 3, co = (it >> 2) & 15, t = it >> 6;
-      *reinterpret_cast<s4*>(&s_w[t][co][4 * q]) = *reinterpret_cast<const s4*>(
-          a.W + ((long long)t * a.cout_p + co0 + co) * a.cin_p + c0 + 4 * q);
-    }
+    commit();
     __syncthreads();
-#pragma unroll 3
-    for (int t = 0; t < 27; ++t) {
-      const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;  // halo coordinates
-      const s4 b = *reinterpret_cast<const s4*>(&s_w[t][m][4 * kq]);
+    if (c0 + 16 < a.cin_p) fetch(c0 + 16);  // in flight during this chunk's MFMAs
+#pragma unroll 1
+    for (int dz = 0; dz < 3; ++dz) {
+      const uint16_t* xp = s_x + xr_base + dz * kCH * kCH * kPitch;
+      const uint16_t* wp = s_w + wr_base + dz * 9 * 16 * NT * kPitch;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int yl = wv * 4 + r;
-        const s4 av = *reinterpret_cast<const s4*>(&s_x[dz][yl + dy][m + dx][4 * kq]);
-        acc[r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b, acc[r], 0, 0, 0);
+      for (int t9 = 0; t9 < 9; ++t9) {
+        const int dy = t9 / 3, dx = t9 % 3;  // halo coordinates
+        s4 w[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+          w[n] = *reinterpret_cast<const s4*>(wp + (t9 * NT + n) * 16 * kPitch);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const s4 xv = *reinterpret_cast<const s4*>(xp + ((r + dy) * kCH + dx) * kPitch);
+#pragma unroll
+          for (int n = 0; n < NT; ++n)
+            acc[n][r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[n], xv, acc[n][r], 0, 0, 0);
+        }
       }
     }
   }
-  // D[4 kq + j][n]: voxel x0 + 4 kq + j of row y0 + 4 wv + r, output channel co0 + n
-  const int co = co0 + m;
-  if (co >= a.cout) return;
-  const float bias = a.bias ? a.bias[co] : 0.0f;
+  // D[4 kq + j][m]: output channel co0 + 16 n + 4 kq + j of voxel x0 + m in
+  // row y0 + 4 wv + r
+  const int x = x0 + m;
+  if (x >= a.nx) return;
+  const bool vec = a.cout % 4 == 0 && a.ldy % 4 == 0 && a.ldf % 4 == 0 &&
+                   (reinterpret_cast<uintptr_t>(a.Y) % 8) == 0 &&
+                   (reinterpret_cast<uintptr_t>(a.yf) % 16) == 0;
+  // voxel of row r: v0 + r nx (v0: this lane's voxel in row y0 + 4 wv)
+  const long long v0 = (long long)(z * a.ny + y0 + wv * 4) * a.nx + x;
+  uint16_t* const yrow = a.Y ? a.Y + v0 * a.ldy : nullptr;
+  float* const frow = a.yf ? a.yf + v0 * a.ldf : nullptr;
+  const long long ystep = (long long)a.nx * a.ldy, fstep = (long long)a.nx * a.ldf;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int y = y0 + wv * 4 + r;
-    if (y >= a.ny) continue;
+  for (int n = 0; n < NT; ++n) {
+    const int cb = co0 + 16 * n + 4 * kq;
+    if (cb >= a.cout) continue;
+    float bias[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int x = x0 + 4 * kq + j;
-      if (x >= a.nx) continue;
-      const long long v = (long long)(z * a.ny + y) * a.nx + x;
-      float o = acc[r][j] + bias;
-      if (a.relu) o = fmaxf(o, 0.0f);
-      if (a.Y) a.Y[v * a.ldy + co] = f2bf(o);
-      if (a.yf) a.yf[v * a.ldf + co] = o;
+    for (int j = 0; j < 4; ++j) bias[j] = (a.bias && cb + j < a.cout) ? a.bias[cb + j] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (y0 + wv * 4 + r >= a.ny) continue;
+      float o[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        o[j] = acc[n][r][j] + bias[j];
+        if (a.relu) o[j] = fmaxf(o[j], 0.0f);
+      }
+      if (vec) {
+        if (yrow) {
+          const bf2 lo = __builtin_convertvector(f2{o[0], o[1]}, bf2);
+          const bf2 hi = __builtin_convertvector(f2{o[2], o[3]}, bf2);
+          *reinterpret_cast<uint2*>(yrow + r * ystep + cb) =
+              uint2{__builtin_bit_cast(unsigned, lo), __builtin_bit_cast(unsigned, hi)};
+        }
+        if (frow) *reinterpret_cast<f4*>(frow + r * fstep + cb) = f4{o[0], o[1], o[2], o[3]};
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (cb + j >= a.cout) continue;
+          if (yrow) yrow[r * ystep + cb + j] = f2bf(o[j]);
+          if (frow) frow[r * fstep + cb + j] = o[j];
+        }
+      }
     }
   }
 }
 
-// Weight gradient, partial over a chunk of (z, y) rows.  One wave per
-// (chunk, 16 input channels, 16 output channels) keeps the 27 tap tiles in
-// registers: A[m][k] = X[voxel k shifted by tap][ci m], B[k][n] = dZ[voxel k][co n]
-// with K running over 16 voxels of a row.  The waves of input block 0 also
-// sum dZ for the bias gradient.
-__global__ void __launch_bounds__(64)
-    k_wgrad(const uint16_t* __restrict__ X, int ldx, int cin, int cin_p,
-            const uint16_t* __restrict__ dZ, int ldz, int cout, int cout_p, int nz, int ny,
-            int nx, int rows_per_chunk, float* __restrict__ part,
-            float* __restrict__ partb) {
-  const int lane = threadIdx.x;
-  const int nci = cin_p / 16, nco = cout_p / 16;
+// Weight gradient, partial over a brick of 16 x 16 (x, y) voxels and a range
+// of z planes.  A block of four waves takes one brick, one tile of 16 input
+// channels and one tile of 16 output channels; it marches through its planes
+// with the input planes z-1, z, z+1 (halo 18 x 18) and the output-gradient
+// plane z staged in LDS channel-major, so that a lane reads the four voxels
+// of its K slots for one channel at once:
+//   A[ci][k] = X[voxel k shifted by tap][ci],  B[k][co] = dZ[voxel k][co]
+// with K running over 16 voxels of a row (lane group g takes voxels 4g..4g+3).
+// Wave w owns rows 4w..4w+3 of the brick and keeps the 27 tap tiles in
+// registers.  For one (dz, dy) a lane reads 6 consecutive halo voxels, which
+// hold the operands of the three x taps (the shift by one voxel is a 16-bit
+// funnel shift of the dwords).  The next planes' loads are in flight during
+// the MFMAs of the current one.  At the end the four waves' tiles are added
+// in LDS in wave order (a fixed order) and the block writes one partial;
+// blocks of input tile 0 also sum dZ for the bias gradient.
+constexpr int kWgPX = 20;   // X^T row pitch (elements): 18 halo voxels + pad (40 bytes)
+constexpr int kWgPD = 20;   // dZ^T row pitch (elements): 16 voxels + pad (40 bytes)
+constexpr int kWgXItems = kCH * kCH * 4;          // 8-byte items per input plane
+constexpr int kWgXPer = (kWgXItems + 255) / 256;  // per thread
+constexpr int kWgDPer = 16 * 16 * 4 / 256;        // dZ items per thread
+constexpr int kWgSlot = kCH * 16 * kWgPX;         // elements per staged input plane
+struct WgradArgs {
+  const uint16_t* X;
+  int ldx, cin, cin_p;
+  const uint16_t* dZ;
+  int ldz, cout, cout_p;
+  int nz, ny, nx;
+  int zper, nzp;  // planes per block, z parts
+  float* part;
+  float* partb;
+};
+__global__ void __launch_bounds__(256, 2) k_wgrad(WgradArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t s_xt[3 * kWgSlot];  // [slot][hy][ci][hx]
+  __shared__ __attribute__((aligned(16))) uint16_t s_dt[16 * 16 * kWgPD];  // [y][co][x]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m = lane & 15, kq = lane >> 4, q = tid & 3;
+  const int nci = a.cin_p / 16, nco = a.cout_p / 16;
+  const int nbx = (a.nx + 15) / 16, nby = (a.ny + 15) / 16;
   int b = blockIdx.x;
   const int cb = b % nco;
   b /= nco;
   const int ib = b % nci;
-  const int ch = b / nci;
-  const int nrows = nz * ny;
-  const int r0 = ch * rows_per_chunk, r1 = min(r0 + rows_per_chunk, nrows);
-  const int m = lane & 15, kq = lane >> 4;
-  const int ci = ib * 16 + m, co = cb * 16 + m;
+  b /= nci;
+  const int chunk = b;  // (z part, brick y, brick x), brick x fastest
+  const int bx = b % nbx;
+  b /= nbx;
+  const int by = b % nby;
+  const int zp = b / nby;
+  const int x0 = bx * 16, y0 = by * 16;
+  const int zb = zp * a.zper, ze = min(a.nz, zb + a.zper);
+  const long long nvox = (long long)a.nz * a.ny * a.nx;
+  const RBuf rx = make_rbuf(
+      a.X, static_cast<unsigned>(((nvox - 1) * a.ldx + ((a.cin + 3) & ~3)) * 2));
+  const RBuf rd = make_rbuf(
+      a.dZ, static_cast<unsigned>(((nvox - 1) * a.ldz + ((a.cout + 3) & ~3)) * 2));
+  // input items of this thread: element offset within a plane (-1: reads 0)
+  // and LDS position (without the slot and channel-in-quad terms)
+  int xoff[kWgXPer], xl[kWgXPer];
+  const bool cin_ok = ib * 16 + 4 * q < a.cin;
+#pragma unroll
+  for (int j = 0; j < kWgXPer; ++j) {
+    const int it = tid + 256 * j;
+    const int p = it >> 2, hy = p / kCH, hx = p % kCH;
+    const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+    const bool ok = it < kWgXItems && cin_ok && (unsigned)gy < (unsigned)a.ny &&
+                    (unsigned)gx < (unsigned)a.nx;
+    xoff[j] = ok ? (gy * a.nx + gx) * a.ldx + ib * 16 + 4 * q : -1;
+    xl[j] = it < kWgXItems ? (hy * 16 + 4 * q) * kWgPX + hx : -1;
+  }
+  // output-gradient items: voxel (x0 + dx_, y0 + dy_) with dy_ = tid / 64 + 4 j
+  const int dx_ = (tid >> 2) & 15;
+  const bool dcol_ok = x0 + dx_ < a.nx && cb * 16 + 4 * q < a.cout;
+  const long long plane_x = (long long)a.ny * a.nx * a.ldx;
+  uint2 px[kWgXPer], pd[kWgDPer];
+  auto fetch_x = [&](int gz) {
+    const bool zok = (unsigned)gz < (unsigned)a.nz;
+#pragma unroll
+    for (int j = 0; j < kWgXPer; ++j) {
+      const unsigned o = zok && xoff[j] >= 0
+                             ? static_cast<unsigned>((gz * plane_x + xoff[j]) * 2)
+                             : kFarOffset;
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(rx.r, o, 0, 0);
+      px[j] = uint2{static_cast<unsigned>(v[0]), static_cast<unsigned>(v[1])};
+    }
+  };
+  auto fetch_d = [&](int gz) {
+#pragma unroll
+    for (int j = 0; j < kWgDPer; ++j) {
+      const int gy = y0 + (tid >> 6) + 4 * j;
+      const bool ok = dcol_ok && gy < a.ny;
+      const long long e =
+          ((long long)(gz * a.ny + gy) * a.nx + x0 + dx_) * a.ldz + cb * 16 + 4 * q;
+      const unsigned o = ok ? static_cast<unsigned>(e * 2) : kFarOffset;
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(rd.r, o, 0, 0);
+      pd[j] = uint2{static_cast<unsigned>(v[0]), static_cast<unsigned>(v[1])};
+    }
+  };
+  // channel-major commits: 4 channels of one voxel go to 4 LDS rows
+  auto commit_x = [&](int slot) {
+    uint16_t* base = s_xt + slot * kWgSlot;
+#pragma unroll
+    for (int j = 0; j < kWgXPer; ++j) {
+      if (xl[j] < 0) continue;
+      uint16_t* d = base + xl[j];
+      d[0] = static_cast<uint16_t>(px[j].x);
+      d[kWgPX] = static_cast<uint16_t>(px[j].x >> 16);
+      d[2 * kWgPX] = static_cast<uint16_t>(px[j].y);
+      d[3 * kWgPX] = static_cast<uint16_t>(px[j].y >> 16);
+    }
+  };
+  auto commit_d = [&]() {
+#pragma unroll
+    for (int j = 0; j < kWgDPer; ++j) {
+      uint16_t* d = s_dt + (((tid >> 6) + 4 * j) * 16 + 4 * q) * kWgPD + dx_;
+      d[0] = static_cast<uint16_t>(pd[j].x);
+      d[kWgPD] = static_cast<uint16_t>(pd[j].x >> 16);
+      d[2 * kWgPD] = static_cast<uint16_t>(pd[j].y);
+      d[3 * kWgPD] = static_cast<uint16_t>(pd[j].y >> 16);
+    }
+  };
   f4 acc[27];
 #pragma unroll
   for (int t = 0; t < 27; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
   float bs = 0.0f;
-  for (int row = r0; row < r1; ++row) {
-    const int z = row / ny, y = row % ny;
-    for (int xb = 0; xb < nx; xb += 16) {
-      s4 bb;
+  // planes zb - 1 and zb, then the march
+  fetch_x(zb - 1);
+  commit_x((zb + 2) % 3);
+  fetch_x(zb);
+  commit_x(zb % 3);
+  fetch_x(zb + 1);
+  fetch_d(zb);
+  for (int z = zb; z < ze; ++z) {
+    __syncthreads();  // the plane z - 2 slot and the dZ plane are no longer read
+    commit_x((z + 1) % 3);
+    commit_d();
+    __syncthreads();
+    if (z + 1 < ze) {
+      fetch_x(z + 2);
+      fetch_d(z + 1);
+    }
+    const uint16_t* xs[3];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int x = xb + 4 * kq + j;
-        bb[j] = (x < nx && co < cout)
-                    ? static_cast<short>(dZ[((long long)row * nx + x) * ldz + co])
-                    : static_cast<short>(0);
-        bs += bf2f(static_cast<uint16_t>(bb[j]));
+    for (int dz = 0; dz < 3; ++dz) xs[dz] = s_xt + ((z + 2 + dz) % 3) * kWgSlot;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int yl = 4 * wv + r;
+      const s4 bv = *reinterpret_cast<const s4*>(&s_dt[(yl * 16 + m) * kWgPD + 4 * kq]);
+      if (ib == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bs += bf2f(static_cast<uint16_t>(bv[i]));
       }
 #pragma unroll
-      for (int t = 0; t < 27; ++t) {
-        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-        const int zz = z + dz, yy = y + dy;
-        const bool rok = ci < cin && (unsigned)zz < (unsigned)nz && (unsigned)yy < (unsigned)ny;
-        const uint16_t* xr = X + (rok ? (long long)(zz * ny + yy) * nx * ldx + ci : 0);
-        s4 av;
+      for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int xx = xb + 4 * kq + j + dx;
-          av[j] = (rok && (unsigned)xx < (unsigned)nx)
-                      ? static_cast<short>(xr[(long long)xx * ldx])
-                      : static_cast<short>(0);
+        for (int dy = 0; dy < 3; ++dy) {
+          // halo voxels 4 kq .. 4 kq + 5 of row yl + dy, channel m
+          const uint16_t* p = xs[dz] + ((yl + dy) * 16 + m) * kWgPX + 4 * kq;
+          const uint2 w01 = *reinterpret_cast<const uint2*>(p);
+          const unsigned w2 = *reinterpret_cast<const unsigned*>(p + 4);
+          const unsigned a0 = __builtin_amdgcn_alignbit(w01.y, w01.x, 16);
+          const unsigned a1 = __builtin_amdgcn_alignbit(w2, w01.y, 16);
+          const s4 opm = __builtin_bit_cast(s4, uint2{w01.x, w01.y});  // dx = -1
+          const s4 op0 = __builtin_bit_cast(s4, uint2{a0, a1});        // dx = 0
+          const s4 opp = __builtin_bit_cast(s4, uint2{w01.y, w2});     // dx = +1
+          const int t = dz * 9 + dy * 3;
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(opm, bv, acc[t], 0, 0, 0);
+          acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(op0, bv, acc[t + 1], 0, 0, 0);
+          acc[t + 2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(opp, bv, acc[t + 2], 0, 0, 0);
         }
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bb, acc[t], 0, 0, 0);
-      }
     }
   }
-  float* out = part + (long long)ch * 27 * cin_p * cout_p;
+  // the four waves' tiles added in LDS in wave order: D[4 kq + j][m] is
+  // (input channel 4 kq + j, output channel m)
+  float* red = reinterpret_cast<float*>(s_xt);  // 27 x 16 x 16 floats
+  __shared__ float red_b[16];
+  bs += __shfl_xor(bs, 16);
+  bs += __shfl_xor(bs, 32);
+  for (int w = 0; w < 4; ++w) {
+    __syncthreads();
+    if (wv == w) {
 #pragma unroll
-  for (int t = 0; t < 27; ++t)
+      for (int t = 0; t < 27; ++t)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      out[((long long)t * cin_p + ib * 16 + 4 * kq + j) * cout_p + cb * 16 + m] = acc[t][j];
-  if (ib == 0) {
-    bs += __shfl_xor(bs, 16);
-    bs += __shfl_xor(bs, 32);
-    if (kq == 0) partb[(long long)ch * cout_p + cb * 16 + m] = bs;
+        for (int j = 0; j < 4; ++j) {
+          float* d = red + (t * 16 + 4 * kq + j) * 16 + m;
+          *d = (w == 0 ? 0.0f : *d) + acc[t][j];
+        }
+      if (kq == 0) red_b[m] = (w == 0 ? 0.0f : red_b[m]) + bs;
+    }
   }
+  __syncthreads();
+  float* out = a.part + (long long)chunk * 27 * a.cin_p * a.cout_p;
+  for (int e = tid; e < 27 * 256; e += 256) {
+    const int t = e >> 8, ci = (e >> 4) & 15, co = e & 15;
+    out[((long long)t * a.cin_p + ib * 16 + ci) * a.cout_p + cb * 16 + co] = red[e];
+  }
+  if (ib == 0 && tid < 16) a.partb[(long long)chunk * a.cout_p + cb * 16 + tid] = red_b[tid];
 }
 
-// dW[t][ci][co] = sum over chunks (in chunk order) of the padded partials.
-__global__ void k_reduce_w(const float* __restrict__ part, int nchunks, int cin, int cout,
-                           int cin_p, int cout_p, float* __restrict__ dW, int accumulate) {
+// dW[t][ci][co] = sum over chunks of the padded partials.  A block of 256
+// threads reduces 16 consecutive outputs: 16 threads per output each sum the
+// chunks c = q, q + 16, ... (q = the thread's share), then the 16 shares are
+// added in order q = 0..15 (a fixed order, so the result does not depend on
+// scheduling).  Many short sums in parallel instead of one long one per
+// output: the partials of a layer can hold thousands of chunks.
+constexpr int kRedShare = 16;
+__global__ void __launch_bounds__(256)
+    k_reduce_w(const float* __restrict__ part, int nchunks, int cin, int cout, int cin_p,
+               int cout_p, float* __restrict__ dW, int accumulate) {
+  __shared__ float red[kRedShare][256 / kRedShare];
   const long long n = 27LL * cin * cout, stride = 27LL * cin_p * cout_p;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
+  const int lo = threadIdx.x % (256 / kRedShare), q = threadIdx.x / (256 / kRedShare);
+  const long long i = (long long)blockIdx.x * (256 / kRedShare) + lo;
+  float s = 0.0f;
+  if (i < n) {
     const int t = static_cast<int>(i / ((long long)cin * cout));
     const int r = static_cast<int>(i % ((long long)cin * cout));
     const long long o = ((long long)t * cin_p + r / cout) * cout_p + r % cout;
-    float s = 0.0f;
-    for (int c = 0; c < nchunks; ++c) s += part[c * stride + o];
-    dW[i] = accumulate ? dW[i] + s : s;
+    for (int c = q; c < nchunks; c += kRedShare) s += part[c * stride + o];
+  }
+  red[q][lo] = s;
+  __syncthreads();
+  if (q == 0 && i < n) {
+    float tot = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kRedShare; ++k) tot += red[k][lo];
+    dW[i] = accumulate ? dW[i] + tot : tot;
   }
 }
 
-__global__ void k_reduce_b(const float* __restrict__ partb, int nchunks, int cout,
-                           int cout_p, float* __restrict__ db, int accumulate) {
-  const int co = blockIdx.x * blockDim.x + threadIdx.x;
-  if (co >= cout) return;
+__global__ void __launch_bounds__(256)
+    k_reduce_b(const float* __restrict__ partb, int nchunks, int cout, int cout_p,
+               float* __restrict__ db, int accumulate) {
+  __shared__ float red[kRedShare][256 / kRedShare];
+  const int lo = threadIdx.x % (256 / kRedShare), q = threadIdx.x / (256 / kRedShare);
+  const int co = blockIdx.x * (256 / kRedShare) + lo;
   float s = 0.0f;
-  for (int c = 0; c < nchunks; ++c) s += partb[(long long)c * cout_p + co];
-  db[co] = accumulate ? db[co] + s : s;
+  if (co < cout)
+    for (int c = q; c < nchunks; c += kRedShare) s += partb[(long long)c * cout_p + co];
+  red[q][lo] = s;
+  __syncthreads();
+  if (q == 0 && co < cout) {
+    float tot = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kRedShare; ++k) tot += red[k][lo];
+    db[co] = accumulate ? db[co] + tot : tot;
+  }
 }
 
 __global__ void k_relu_mask(uint16_t* __restrict__ d, int ldd, const uint16_t* __restrict__ a,
@@ -499,23 +767,38 @@ unsigned grid_n(long long n) {
   return static_cast<unsigned>(b);
 }
 
-// Row chunking of the weight gradient: about 4096 waves in total.
-void wgrad_chunks(int cin_p, int cout_p, int nz, int ny, int& nchunks, int& rpc) {
-  const int nrows = nz * ny;
-  const int per = (cin_p / 16) * (cout_p / 16);
-  int want = (4096 + per - 1) / per;
-  if (want > nrows) want = nrows;
+// Split of the weight gradient over z: about 512 blocks in total (two per
+// compute unit), each marching through zper planes of one brick.
+void wgrad_split(int cin_p, int cout_p, int nz, int ny, int nx, int& zper, int& nzp) {
+  const long long per = (long long)(cin_p / 16) * (cout_p / 16) * ((nx + 15) / 16) *
+                        ((ny + 15) / 16);
+  long long want = (512 + per - 1) / per;
+  if (want > nz) want = nz;
   if (want < 1) want = 1;
-  rpc = (nrows + want - 1) / want;
-  nchunks = (nrows + rpc - 1) / rpc;
+  zper = static_cast<int>((nz + want - 1) / want);
+  nzp = (nz + zper - 1) / zper;
+}
+long long wgrad_chunks(int cin_p, int cout_p, int nz, int ny, int nx) {
+  int zper, nzp;
+  wgrad_split(cin_p, cout_p, nz, ny, nx, zper, nzp);
+  return (long long)nzp * ((ny + 15) / 16) * ((nx + 15) / 16);
 }
 
 }  // namespace
 
 hipError_t unet_conv(const ConvArgs& a, hipStream_t s) {
-  if (a.ldx % 4 == 0 && (reinterpret_cast<uintptr_t>(a.X) % 8) == 0) {
-    dim3 grid((a.nx + kCT - 1) / kCT, (a.ny + kCT - 1) / kCT, a.nz * (a.cout_p / 16));
-    hipLaunchKernelGGL(k_conv_tile, grid, dim3(256), 0, s, a);
+  const long long tile_bytes =
+      ((long long)a.nz * a.ny * a.nx * a.ldx + ((a.cin_valid + 3) & ~3)) * 2;
+  if (a.ldx % 4 == 0 && (reinterpret_cast<uintptr_t>(a.X) % 8) == 0 &&
+      tile_bytes < static_cast<long long>(kFarOffset) - 16) {
+    // 32 output channels per block where the layer has them: each input
+    // operand read from LDS then feeds two MFMAs
+    const int nt = a.cout_p % 32 == 0 ? 2 : 1;
+    dim3 grid((a.nx + kCT - 1) / kCT, (a.ny + kCT - 1) / kCT, a.nz * (a.cout_p / (16 * nt)));
+    if (nt == 2)
+      hipLaunchKernelGGL(k_conv_tile<2>, grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL(k_conv_tile<1>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
   }
   dim3 grid((a.nx + 63) / 64, a.ny, a.nz * (a.cout_p / 16));
@@ -528,30 +811,35 @@ hipError_t unet_conv(const ConvArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-long long unet_wgrad_part_floats(int cin_p, int cout_p, int nz, int ny) {
-  int nch, rpc;
-  wgrad_chunks(cin_p, cout_p, nz, ny, nch, rpc);
-  return (long long)nch * 27 * cin_p * cout_p;
+long long unet_wgrad_part_floats(int cin_p, int cout_p, int nz, int ny, int nx) {
+  return wgrad_chunks(cin_p, cout_p, nz, ny, nx) * 27 * cin_p * cout_p;
 }
 
-long long unet_wgrad_bias_floats(int cin_p, int cout_p, int nz, int ny) {
-  int nch, rpc;
-  wgrad_chunks(cin_p, cout_p, nz, ny, nch, rpc);
-  return (long long)nch * cout_p;
+long long unet_wgrad_bias_floats(int cin_p, int cout_p, int nz, int ny, int nx) {
+  return wgrad_chunks(cin_p, cout_p, nz, ny, nx) * cout_p;
 }
 
 hipError_t unet_wgrad(const uint16_t* X, int ldx, int cin, int cin_p, const uint16_t* dZ,
                       int ldz, int cout, int cout_p, int nz, int ny, int nx, float* part,
                       float* partb, float* dW, float* db, int accumulate, hipStream_t s) {
-  int nch, rpc;
-  wgrad_chunks(cin_p, cout_p, nz, ny, nch, rpc);
+  // both tensors are read through 32-bit byte offsets
+  const long long nvox = (long long)nz * ny * nx;
+  if ((nvox * ldx + 4) * 2 >= static_cast<long long>(kFarOffset) ||
+      (nvox * ldz + 4) * 2 >= static_cast<long long>(kFarOffset) || ldx % 4 || ldz % 4 ||
+      reinterpret_cast<uintptr_t>(X) % 8 || reinterpret_cast<uintptr_t>(dZ) % 8)
+    return hipErrorInvalidValue;
+  WgradArgs w{X, ldx, cin, cin_p, dZ, ldz, cout, cout_p, nz, ny, nx, 0, 0, part, partb};
+  wgrad_split(cin_p, cout_p, nz, ny, nx, w.zper, w.nzp);
+  const long long nch = wgrad_chunks(cin_p, cout_p, nz, ny, nx);
   const unsigned blocks = static_cast<unsigned>(nch * (cin_p / 16) * (cout_p / 16));
-  hipLaunchKernelGGL(k_wgrad, dim3(blocks), dim3(64), 0, s, X, ldx, cin, cin_p, dZ, ldz,
-                     cout, cout_p, nz, ny, nx, rpc, part, partb);
-  hipLaunchKernelGGL(k_reduce_w, dim3(grid_n(27LL * cin * cout)), dim3(256), 0, s, part,
-                     nch, cin, cout, cin_p, cout_p, dW, accumulate);
-  hipLaunchKernelGGL(k_reduce_b, dim3((cout + 127) / 128), dim3(128), 0, s, partb, nch,
-                     cout, cout_p, db, accumulate);
+  hipLaunchKernelGGL(k_wgrad, dim3(blocks), dim3(256), 0, s, w);
+  const long long nw = 27LL * cin * cout, per = 256 / kRedShare;
+  hipLaunchKernelGGL(k_reduce_w, dim3(static_cast<unsigned>((nw + per - 1) / per)), dim3(256),
+                     0, s, part, static_cast<int>(nch), cin, cout, cin_p, cout_p, dW,
+                     accumulate);
+  hipLaunchKernelGGL(k_reduce_b, dim3(static_cast<unsigned>((cout + per - 1) / per)),
+                     dim3(256), 0, s, partb, static_cast<int>(nch), cout, cout_p, db,
+                     accumulate);
   return hipGetLastError();
 }
 

@@ -38,8 +38,9 @@ hipError_t unet_conv(const ConvArgs& a, hipStream_t s);
 // written unpadded ([27][cin][cout], [cout], FP32; accumulate = 1 adds to
 // dW, db).  `part` and `partb` are
 // workspaces of unet_wgrad_part_floats / unet_wgrad_bias_floats floats.
-long long unet_wgrad_part_floats(int cin_p, int cout_p, int nz, int ny);
-long long unet_wgrad_bias_floats(int cin_p, int cout_p, int nz, int ny);
+// X and dZ: channel strides and element offsets multiples of 4 (8-byte items).
+long long unet_wgrad_part_floats(int cin_p, int cout_p, int nz, int ny, int nx);
+long long unet_wgrad_bias_floats(int cin_p, int cout_p, int nz, int ny, int nx);
 hipError_t unet_wgrad(const uint16_t* X, int ldx, int cin, int cin_p, const uint16_t* dZ,
                       int ldz, int cout, int cout_p, int nz, int ny, int nx, float* part,
                       float* partb, float* dW, float* db, int accumulate, hipStream_t s);

@@ -2,7 +2,7 @@
 kernel-trace durations per kernel and grid size.
 
     python -m paper_2603_19371_amd.pmc_summary trace --trace T.csv \\
-        --workload brain160x192x224_f32_w7 --command "..." [--out F.txt]
+        --workload brain160x192x224_f32_w7 --command "..." [--out F.txt] [--top 40]
 
     python -m paper_2603_19371_amd.pmc_summary counters \\
         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \\
@@ -101,7 +101,9 @@ def copy_scale(path, counter, nbytes):
 def _short(name: str) -> str:
     n = name.replace("(anonymous namespace)::", "").replace("lmr::", "")
     n = n.replace("void ", "")
-    return n.split("(")[0]
+    n = n.split("(")[0]
+    # library kernels (rocBLAS / composable_kernel) carry very long names
+    return n if len(n) <= 72 else n[:64] + "...(" + str(len(n)) + ")"
 
 
 def trace_summary(a):
@@ -116,9 +118,16 @@ def trace_summary(a):
              f"# command: {a.command}",
              "# kernel | grid (work-items) | dispatches | mean us | min us | max us | "
              "share of kernel time"]
-    for (k, grid), v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+    rows = sorted(per.items(), key=lambda kv: -sum(kv[1]))
+    for (k, grid), v in rows[:a.top]:
         lines.append(f"{k} | {grid} | {len(v)} | {statistics.mean(v):.2f} | {min(v):.2f} | "
                      f"{max(v):.2f} | {100 * sum(v) / total:.1f}%")
+    rest = rows[a.top:]
+    if rest:
+        t_rest = sum(sum(v) for _, v in rest)
+        lines.append(f"# {len(rest)} more (kernel, grid) rows: "
+                     f"{sum(len(v) for _, v in rest)} dispatches, "
+                     f"{100 * t_rest / total:.1f}% of kernel time")
     lines.append(f"# total kernel time {total * 1e-3:.2f} ms")
     out = a.out or os.path.join(ROOT, "profiles", f"kernels__{a.workload}.txt")
     with open(out, "w") as fh:
@@ -133,6 +142,7 @@ def main():
     for k in ("trace", "workload", "command"):
         t.add_argument("--" + k, required=True)
     t.add_argument("--out")
+    t.add_argument("--top", type=int, default=40, help="rows kept (by total time)")
     c = sub.add_parser("counters")
     for k in ("fetch", "write", "copy-fetch", "copy-write", "kernel", "name", "workload",
               "command"):
