@@ -104,6 +104,19 @@ typedef enum {
   LMR_SIM_MI = 3
 } lmr_similarity;
 
+/* How the three stencil passes (LNCC forward and backward, Gaussian) tile
+ * the volume.  LMR_STENCIL_MARCH: 32 x 8 columns marching through chunks of
+ * z planes (large volumes).  LMR_STENCIL_CUBE: 8^3 cubes of outputs, each
+ * reduced along z, y and x in three steps (small volumes, where a march is
+ * latency).  LMR_STENCIL_AUTO (default): cubes up to 2^20 voxels, else the
+ * march.  The two forms sum the same terms in different orders (FP64 or
+ * compensated sums either way). */
+typedef enum {
+  LMR_STENCIL_AUTO = 0,
+  LMR_STENCIL_MARCH = 1,
+  LMR_STENCIL_CUBE = 2
+} lmr_stencil_form;
+
 /* Hyper-parameters of one registration.  The paper's own setting
  * (Sec. 3: lambda0 = 0.006, mu+ = 1.5, mu- = 0.975, no rejection) and the
  * synthetic-phantom setting (lambda x2 / x0.5, rejection with tau = 0) are
@@ -134,6 +147,7 @@ typedef struct {
   double adam_eps;     /* > 0 (default 1e-8) */
   int    similarity;   /* lmr_similarity (default LMR_SIM_LNCC) */
   int    mi_bins;      /* bins per image of LMR_SIM_MI, 8..32 (default 32) */
+  int    stencil;      /* lmr_stencil_form (default LMR_STENCIL_AUTO) */
 } lmr_params;
 
 /* The whole optimizer state of one pair: the scalar damping and the loss
@@ -337,7 +351,8 @@ void lmr_pyramid_destroy(lmr_pyramid* pyr);
  * HIP graph on first use and replayed.  The batch owns a non-blocking stream;
  * results of one pair are read through lmr_batch_pair (borrowed context).
  * Box side 3..9 and Gaussian radius ceil(3 sigma) <= 4 are supported (else
- * LMR_EINVAL).  A barrier wait longer than 0.25 s (which means the blocks
+ * LMR_EINVAL).  Its stencils march (LMR_STENCIL_MARCH, whatever p->stencil
+ * says), so a pair follows a stand-alone context with that form bit for bit.  A barrier wait longer than 0.25 s (which means the blocks
  * were not all resident) makes every block leave; lmr_batch_sync reports it
  * as LMR_EHIP.  The persistent launch needs all its blocks resident at once:
  * kernels running at the same time on other streams (another batch's steps

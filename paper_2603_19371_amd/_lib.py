@@ -30,6 +30,10 @@ class LmrError(RuntimeError):
     pass
 
 
+# lmr_stencil_form
+LMR_STENCIL_AUTO, LMR_STENCIL_MARCH, LMR_STENCIL_CUBE = 0, 1, 2
+
+
 class Params(C.Structure):
     """Mirror of lmr_params."""
     _fields_ = [("window", C.c_int), ("grad_sigma", C.c_double),
@@ -40,7 +44,8 @@ class Params(C.Structure):
                 ("tau", C.c_double), ("max_retries", C.c_int),
                 ("tile", C.c_int), ("optimizer", C.c_int), ("adam_lr", C.c_double),
                 ("adam_beta1", C.c_double), ("adam_beta2", C.c_double),
-                ("adam_eps", C.c_double), ("similarity", C.c_int), ("mi_bins", C.c_int)]
+                ("adam_eps", C.c_double), ("similarity", C.c_int), ("mi_bins", C.c_int),
+                ("stencil", C.c_int)]
 
     @staticmethod
     def make(**kw) -> "Params":

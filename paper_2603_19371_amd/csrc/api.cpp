@@ -42,6 +42,9 @@ bool lmr::params_ok(const lmr_params* p) {
       p->similarity != LMR_SIM_DEMONS && p->similarity != LMR_SIM_MI)
     return false;
   if (p->similarity == LMR_SIM_MI && (p->mi_bins < 8 || p->mi_bins > 32)) return false;
+  if (p->stencil != LMR_STENCIL_AUTO && p->stencil != LMR_STENCIL_MARCH &&
+      p->stencil != LMR_STENCIL_CUBE)
+    return false;
   if (p->similarity == LMR_SIM_DEMONS && (p->optimizer != LMR_OPT_LM || p->tile != 1))
     return false;
   if (p->optimizer == LMR_OPT_ADAM) {
@@ -193,6 +196,7 @@ void lmr_default_params(lmr_params* p) {
   p->adam_eps = 1e-8;
   p->similarity = LMR_SIM_LNCC;
   p->mi_bins = 32;
+  p->stencil = LMR_STENCIL_AUTO;
 }
 
 lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
@@ -215,7 +219,7 @@ lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
                        p->adam_beta1, p->adam_beta2,     p->similarity,
                        p->mi_bins};
   c->stream = stream;
-  c->nparts = fwd_num_blocks(c->g, p->window);
+  c->nparts = fwd_num_blocks(c->g, *p);
 
   const size_t f3 = align256(sizeof(float) * 3 * N);
   const size_t sizes[] = {f3,

@@ -170,9 +170,12 @@ lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes, lmr_
   b->ctx.resize(npairs, nullptr);
   b->host.resize(npairs);
   b->partials.resize(npairs, nullptr);
+  // the persistent kernel's stencils march; the pairs' own begin does too
+  lmr_params pc = *p;
+  pc.stencil = LMR_STENCIL_MARCH;
   for (int i = 0; i < npairs; ++i) {
     const int nz = shapes[3 * i], ny = shapes[3 * i + 1], nx = shapes[3 * i + 2];
-    lmr_status st = lmr_create(&b->ctx[i], nz, ny, nx, img, p, b->stream);
+    lmr_status st = lmr_create(&b->ctx[i], nz, ny, nx, img, &pc, b->stream);
     if (st != LMR_OK) return fail(st);
     lmr_ctx* c = b->ctx[i];
     // partial slots for the largest tile count any tuning can produce (cz >= 2)

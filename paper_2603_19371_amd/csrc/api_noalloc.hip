@@ -75,7 +75,7 @@ extern "C" lmr_status lmr_loss_grad_noalloc(const void* F, const void* M, lmr_dt
   const long long N = (long long)nz * ny * nx;
   if (N > kMaxVoxels) return LMR_EINVAL;  // beyond the static workspace
   const Geom g{nz, ny, nx, N};
-  const int nparts = fwd_num_blocks(g, p->window);
+  const int nparts = fwd_num_blocks(g, *p);
   if (nparts > kMaxParts) return LMR_EINVAL;
   char* base = nullptr;
   const lmr_status st = scratch_of_current_device(&base);

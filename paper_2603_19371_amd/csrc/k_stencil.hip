@@ -47,10 +47,46 @@ __global__ void __launch_bounds__(kTX* TY)
   pol.end_tile(loc, tile);  // partials in tile order, as in the batched form
 }
 
+// The same stencil on kT3^3 cubes (small volumes; stencil.h).
+template <int R, class P>
+__global__ void __launch_bounds__(kCubeThreads)
+    k_cube(const P pol, Geom g, int cubes_x, int cubes_y, const DevState* st, int need) {
+  if (st && need) {
+    if (st->stalled) return;
+    if (need == 2 && !st->accepted) return;
+  }
+  __shared__ CubeLds<R, P> sm;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int x0 = (b % cubes_x) * kT3, y0 = ((b / cubes_x) % cubes_y) * kT3;
+  const int z0 = (b / (cubes_x * cubes_y)) * kT3;
+  typename P::Local loc = pol.begin_block(st);
+  stencil_cube<R>(pol, g, x0, y0, z0, loc, sm);
+  pol.end_tile(loc, b);
+}
+
 Tiling tiling_of(const Geom& g) { return make_tiling(g.nz, g.ny, g.nx, kTY); }
 
+// Volumes of at most this many voxels run on cubes under LMR_STENCIL_AUTO
+// (the half- and quarter-resolution levels of a brain-sized pair).
+constexpr long long kCubeMaxVoxels = 1LL << 20;
+
+bool use_cubes(const Geom& g, const lmr_params& p) {
+  return p.stencil == LMR_STENCIL_CUBE ||
+         (p.stencil == LMR_STENCIL_AUTO && g.N <= kCubeMaxVoxels);
+}
+
+int cube_count(const Geom& g) {
+  return ((g.nx + kT3 - 1) / kT3) * ((g.ny + kT3 - 1) / kT3) * ((g.nz + kT3 - 1) / kT3);
+}
+
 template <class P, int R>
-hipError_t run(const P& pol, const Geom& g, const DevState* st, int need, hipStream_t s) {
+hipError_t run(const P& pol, const Geom& g, bool cubes, const DevState* st, int need,
+               hipStream_t s) {
+  if (cubes) {
+    hipLaunchKernelGGL((k_cube<R, P>), dim3(cube_count(g)), dim3(kCubeThreads), 0, s, pol, g,
+                       (g.nx + kT3 - 1) / kT3, (g.ny + kT3 - 1) / kT3, st, need);
+    return hipGetLastError();
+  }
   const Tiling t = tiling_of(g);
   hipLaunchKernelGGL((k_stencil<R, kTY, P>), dim3(t.tiles()), dim3(kTX * kTY), 0, s, pol,
                      g, t, st, need);
@@ -58,13 +94,13 @@ hipError_t run(const P& pol, const Geom& g, const DevState* st, int need, hipStr
 }
 
 template <class P>
-hipError_t run_box(const P& pol, int window, const Geom& g, const DevState* st, int need,
-                   hipStream_t s) {
+hipError_t run_box(const P& pol, int window, const Geom& g, bool cubes, const DevState* st,
+                   int need, hipStream_t s) {
   switch (window / 2) {
-    case 1: return run<P, 1>(pol, g, st, need, s);
-    case 2: return run<P, 2>(pol, g, st, need, s);
-    case 3: return run<P, 3>(pol, g, st, need, s);
-    case 4: return run<P, 4>(pol, g, st, need, s);
+    case 1: return run<P, 1>(pol, g, cubes, st, need, s);
+    case 2: return run<P, 2>(pol, g, cubes, st, need, s);
+    case 3: return run<P, 3>(pol, g, cubes, st, need, s);
+    case 4: return run<P, 4>(pol, g, cubes, st, need, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -77,7 +113,7 @@ hipError_t fstat_t(const T* F, const Geom& g, const lmr_params& p, double* fstat
   pol.fstat = fstat;
   pol.N = static_cast<int>(g.N);
   pol.inv_n = 1.0 / ((double)p.window * p.window * p.window);
-  return run_box(pol, p.window, g, nullptr, 0, s);
+  return run_box(pol, p.window, g, use_cubes(g, p), nullptr, 0, s);
 }
 
 template <typename T, typename Acc>
@@ -94,7 +130,7 @@ hipError_t fwd_t(const T* F, const float* Mw, const double* fstat, const Geom& g
   pol.N = static_cast<int>(g.N);
   pol.inv_n = 1.0 / ((double)p.window * p.window * p.window);
   pol.eps = p.cc_eps;
-  return run_box(pol, p.window, g, st, 1, s);
+  return run_box(pol, p.window, g, use_cubes(g, p), st, 1, s);
 }
 
 template <typename T, typename Acc>
@@ -114,23 +150,25 @@ hipError_t bwd_t(const T* F, const T* M, const float* Mw, const float* maps,
   pol.graw = graw;
   pol.g = g;
   pol.inv_n = 1.0 / ((double)p.window * p.window * p.window);
-  return run_box(pol, p.window, g, st, 2, s);
+  return run_box(pol, p.window, g, use_cubes(g, p), st, 2, s);
 }
 
 template <int R>
-hipError_t smooth_r(const float* in, float* out, const Geom& g, double sigma,
+hipError_t smooth_r(const float* in, float* out, const Geom& g, const lmr_params& p,
                     const DevState* st, hipStream_t s) {
   SmoothPol<R> pol;
   pol.in = in;
   pol.out = out;
   pol.N = static_cast<int>(g.N);
-  gauss_taps<R>(sigma, pol.w);
-  return run<SmoothPol<R>, R>(pol, g, st, 2, s);
+  gauss_taps<R>(p.grad_sigma, pol.w);
+  return run<SmoothPol<R>, R>(pol, g, use_cubes(g, p), st, 2, s);
 }
 
 }  // namespace
 
-int fwd_num_blocks(const Geom& g, int) { return tiling_of(g).tiles(); }
+int fwd_num_blocks(const Geom& g, const lmr_params& p) {
+  return use_cubes(g, p) ? cube_count(g) : tiling_of(g).tiles();
+}
 
 int gauss_radius(double sigma) {
   if (!(sigma > 0.0)) return 0;
@@ -185,13 +223,13 @@ hipError_t launch_bwd(const void* F, const void* M, lmr_dtype t, const float* Mw
 hipError_t launch_smooth(const float* graw, const Geom& g, const lmr_params& p,
                          const DevState* st, float* out, hipStream_t s) {
   switch (gauss_radius(p.grad_sigma)) {
-    case 0: return smooth_r<0>(graw, out, g, p.grad_sigma, st, s);
-    case 1: return smooth_r<1>(graw, out, g, p.grad_sigma, st, s);
-    case 2: return smooth_r<2>(graw, out, g, p.grad_sigma, st, s);
-    case 3: return smooth_r<3>(graw, out, g, p.grad_sigma, st, s);
-    case 4: return smooth_r<4>(graw, out, g, p.grad_sigma, st, s);
-    case 5: return smooth_r<5>(graw, out, g, p.grad_sigma, st, s);
-    case 6: return smooth_r<6>(graw, out, g, p.grad_sigma, st, s);
+    case 0: return smooth_r<0>(graw, out, g, p, st, s);
+    case 1: return smooth_r<1>(graw, out, g, p, st, s);
+    case 2: return smooth_r<2>(graw, out, g, p, st, s);
+    case 3: return smooth_r<3>(graw, out, g, p, st, s);
+    case 4: return smooth_r<4>(graw, out, g, p, st, s);
+    case 5: return smooth_r<5>(graw, out, g, p, st, s);
+    case 6: return smooth_r<6>(graw, out, g, p, st, s);
     default: return hipErrorInvalidValue;
   }
 }

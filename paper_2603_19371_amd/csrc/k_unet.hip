@@ -715,12 +715,20 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_mse_final(const double* __restrict__ part, int n, double inv,
-                            double* __restrict__ loss) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One block of 256 threads: thread t sums partials t, t + 256, ... in order,
+// then a fixed tree adds the 256 sums (the result does not depend on timing).
+__global__ void __launch_bounds__(256)
+    k_mse_final(const double* __restrict__ part, int n, double inv, double* __restrict__ loss) {
+  __shared__ double sh[256];
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += part[i];
-  *loss = s * inv;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = sh[0] * inv;
 }
 
 __global__ void k_fill_u16(uint16_t* __restrict__ p, long long n) {
@@ -914,7 +922,7 @@ hipError_t unet_mse(const float* yf, int ldf, const float* target, float tscale,
   const int nb = unet_mse_blocks(N);
   hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, yf, ldf, target, tscale, N, dout, ld,
                      part);
-  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, s, part, nb,
+  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(256), 0, s, part, nb,
                      1.0 / (3.0 * static_cast<double>(N)), loss);
   return hipGetLastError();
 }

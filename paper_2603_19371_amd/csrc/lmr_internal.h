@@ -377,7 +377,7 @@ struct StepBuffers {
   double* probe;    // scalar loss written by the probe reduction
 };
 
-int fwd_num_blocks(const Geom& g, int window);
+int fwd_num_blocks(const Geom& g, const lmr_params& p);
 int gauss_radius(double sigma);
 
 hipError_t launch_warp(const void* M, lmr_dtype t, const float* u, const Geom& g,

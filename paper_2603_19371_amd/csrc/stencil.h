@@ -268,6 +268,97 @@ __device__ __forceinline__ void stencil_tile(const P& pol, const Geom& g, int x0
   }
 }
 
+// ------------------------------------------------------------- 3D tiles
+// Small volumes (coarse pyramid levels) have too few 32 x TY columns to fill
+// the GPU, and the plane-serial march of a short chunk is their latency.
+// There a block owns a whole kT3^3 cube of outputs instead: each thread
+// reads one (y, x) column of the (kT3 + 2R)^2 halo straight from memory (all
+// its loads in flight at once) and reduces along z, expanding the raw inputs
+// into the accumulated channels; then the block reduces along y and along x
+// in LDS and emits.  Three steps with two barriers instead of a march.
+constexpr int kT3 = 8;
+constexpr int kCubeThreads = 256;
+
+template <int R, class P>
+struct CubeLds {
+  typename P::Acc z[P::NCH][kT3][kT3 + 2 * R][kT3 + 2 * R];
+  typename P::Acc y[P::NCH][kT3][kT3][kT3 + 2 * R];
+};
+
+template <int R, class P>
+__device__ __forceinline__ void stencil_cube(const P& pol, const Geom& g, int x0, int y0,
+                                             int z0, typename P::Local& loc,
+                                             CubeLds<R, P>& sm) {
+  using A = typename P::Acc;
+  constexpr int NR = P::NRAW, NC = P::NCH, W = 2 * R + 1, L = kT3 + 2 * R;
+  constexpr int NT = kCubeThreads;
+  // z: one (y, x) column of the halo per thread
+  for (int col = threadIdx.x; col < L * L; col += NT) {
+    const int yy = col / L, xx = col - yy * L;
+    const int gy = y0 - R + yy, gx = x0 - R + xx;
+    const bool in = (unsigned)gy < (unsigned)g.ny && (unsigned)gx < (unsigned)g.nx;
+    float r[L][NR];
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+      const int gz = z0 - R + k;
+      const unsigned i = (in && (unsigned)gz < (unsigned)g.nz)
+                             ? static_cast<unsigned>((gz * g.ny + gy) * g.nx + gx)
+                             : kFarIndex;
+      pol.load(loc, i, r[k]);
+    }
+#pragma unroll
+    for (int oz = 0; oz < kT3; ++oz) {
+      A a[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) a[c] = A();
+#pragma unroll
+      for (int k = 0; k < W; ++k) pol.accum(a, r[oz + k], k);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sm.z[c][oz][yy][xx] = a[c];
+    }
+  }
+  __syncthreads();
+  // y
+  for (int it = threadIdx.x; it < kT3 * kT3 * L; it += NT) {
+    const int oz = it / (kT3 * L), rem = it - oz * (kT3 * L);
+    const int oy = rem / L, xx = rem - oy * L;
+    A a[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) a[c] = A();
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        if constexpr (P::kBox)
+          a[c] += sm.z[c][oz][oy + k][xx];
+        else
+          a[c] = fma(A(pol.wt(k)), sm.z[c][oz][oy + k][xx], a[c]);
+      }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sm.y[c][oz][oy][xx] = a[c];
+  }
+  __syncthreads();
+  // x, and the outputs
+  for (int it = threadIdx.x; it < kT3 * kT3 * kT3; it += NT) {
+    const int oz = it / (kT3 * kT3), oy = (it / kT3) % kT3, ox = it % kT3;
+    A a[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) a[c] = A();
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        if constexpr (P::kBox)
+          a[c] += sm.y[c][oz][oy][ox + k];
+        else
+          a[c] = fma(A(pol.wt(k)), sm.y[c][oz][oy][ox + k], a[c]);
+      }
+    const int gx = x0 + ox, gy = y0 + oy, gz = z0 + oz;
+    if (gx < g.nx && gy < g.ny && gz < g.nz)
+      pol.emit(loc, (gz * g.ny + gy) * g.nx + gx, gx, gy, gz, a);
+  }
+}
+
 // Block sum of one double per thread; thread 0 writes it to *out.
 template <int NT>
 __device__ __forceinline__ void block_sum_to(double v, double* out) {

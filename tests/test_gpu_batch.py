@@ -38,12 +38,12 @@ def host(t):
 @pytest.mark.parametrize("accum", [0, 1])
 def test_batch_matches_per_pair_runs(L, pairs, accum):
     """Every pair of the batch follows exactly (bitwise) the run of a
-    stand-alone context: same kernels, same tiling, same reduction order;
-    with either box-sum accumulator."""
+    stand-alone context with marching stencils: same kernels, same tiling,
+    same reduction order; with either box-sum accumulator."""
     n = 6
     ref = []
     for (F, M), sh in zip(pairs, SHAPES):
-        c = L.Context(sh, window=5, accum=accum)
+        c = L.Context(sh, window=5, accum=accum, stencil=L.LMR_STENCIL_MARCH)
         c.begin(F, M)
         c.step(F, M, n)
         ref.append((host(c.field()), c.state()))
@@ -64,7 +64,7 @@ def test_batch_matches_staged_per_pair_run(L):
     sh = (67, 100, 330)
     ph = phantoms.brain(sh, seed=7)
     F, M = torch.from_numpy(ph.F).cuda(), torch.from_numpy(ph.M).cuda()
-    c = L.Context(sh, window=5)
+    c = L.Context(sh, window=5, stencil=L.LMR_STENCIL_MARCH)
     c.begin(F, M)
     c.step(F, M, 3)
     ref, st_ref = host(c.field()), c.state()

@@ -108,18 +108,25 @@ def test_warp_integer_shift_is_exact(L):
 
 
 # ------------------------------------------------------------------ loss and gradients
+# the two tilings of the stencil passes: 32 x 8 columns marching through z
+# chunks, and 8^3 cubes (the default below 2^20 voxels)
+STENCILS = [1, 2]
+
+
+@pytest.mark.parametrize("stencil", STENCILS)
 @pytest.mark.parametrize("window,sigma", [(3, 1.0), (5, 0.7), (7, 1.0), (9, 1.6)])
-def test_loss_and_gradients_match_oracle(L, orc, window, sigma):
+def test_loss_and_gradients_match_oracle(L, orc, window, sigma, stencil):
     F, M = smooth_pair(RAGGED, 10 + window)
     rng = np.random.default_rng(11)
     u = (rng.uniform(-2, 2, (3,) + RAGGED)).astype(np.float32)
-    ctx = L.Context(RAGGED, window=window, grad_sigma=sigma)
+    ctx = L.Context(RAGGED, window=window, grad_sigma=sigma, stencil=stencil)
     loss, gr, gs, cc = ctx.loss_grad(dev(F), dev(M), dev(u), cc=True)
     rL, rg = orc.loss_grad(F, M, u, window, 1e-5)
     rMw = orc.warp(M, u)
     _, rcc = orc.lncc(F, rMw, window, 1e-5, with_map=True)
     rgs = orc.gauss(rg, sigma)
-    print(f"[loss w={window}] gpu={loss:.12f} oracle={rL:.12f}", flush=True)
+    print(f"[loss w={window} stencil={stencil}] gpu={loss:.12f} oracle={rL:.12f}",
+          flush=True)
     assert abs(loss - rL) < 2e-7
     e = report("cc", host(cc), rcc)
     assert e < 2e-6, e
@@ -130,15 +137,16 @@ def test_loss_and_gradients_match_oracle(L, orc, window, sigma):
     assert e < 2e-5 * gmax, e
 
 
+@pytest.mark.parametrize("stencil", STENCILS)
 @pytest.mark.parametrize("window,sigma", [(5, 0.7), (9, 1.6)])
-def test_compensated_fp32_sums_match_oracle(L, orc, window, sigma):
+def test_compensated_fp32_sums_match_oracle(L, orc, window, sigma, stencil):
     """Box sums kept as unevaluated FP32 pairs (LMR_ACC_F32C) carry about
     twice FP32's significand, so loss and gradients meet the same bounds as
     the FP64 sums."""
     F, M = smooth_pair(RAGGED, 30 + window)
     rng = np.random.default_rng(12)
     u = (rng.uniform(-2, 2, (3,) + RAGGED)).astype(np.float32)
-    ctx = L.Context(RAGGED, window=window, grad_sigma=sigma, accum=1)
+    ctx = L.Context(RAGGED, window=window, grad_sigma=sigma, accum=1, stencil=stencil)
     loss, gr, gs, cc = ctx.loss_grad(dev(F), dev(M), dev(u), cc=True)
     rL, rg = orc.loss_grad(F, M, u, window, 1e-5)
     rMw = orc.warp(M, u)
