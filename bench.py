@@ -31,9 +31,9 @@ Printed on one JSON line, with
                 skips these).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--workload brain|lung|abdomen|batch|unet] [--accum f64|f32c]
+                    [--workload brain|lung|abdomen|batch|small|unet] [--accum f64|f32c]
 
-The default workload is the brain registration above.  Four more workloads
+The default workload is the brain registration above.  Five more workloads
 print a line of the same form:
   lung     384^3 lung-CT-like pair with BF16 images (FP32 field, FP64 loss),
            pyramid 2x/1x with 100/50 attempts;
@@ -43,6 +43,9 @@ print a line of the same form:
            4 x 160x192x224, 4 x 192x160x256) advanced together, one persistent
            launch per attempt replayed from a HIP graph, tiling autotuned,
            150 attempts at full resolution.
+  small    64 brain-like 48^3 pairs, 50 attempts each: the batched form
+           against the same pairs as stand-alone contexts (graph replays),
+           one after another and on four streams.
   unet     the learned initializer's network at 80x96x112: forward passes/s
            and one training step, with its MFMA roofline (TFLOP/s of the 15
            convolutions against 2.5 PFLOP/s BF16).
@@ -203,6 +206,17 @@ def _pyramid_line(a, F, M, img_dtype, factors, iters, workload, s):
         per_level.append({"factor": f, "voxels": n, "attempts": int(st["attempts"]),
                           "accepted_loss": st["loss"], "lambda": st["lambda_"]})
         vox_att += n * int(st["attempts"])
+    # mean kernel times per attempt at every level: one more registration
+    # outside the timed region with every level's kernels timed (a timed
+    # level runs its attempts eagerly rather than as a graph replay)
+    for l in range(len(factors)):
+        pyr.level(l).profile_start(max_attempts=iters[l], stride=1)
+    pyr.run(F, M, iters, lambda0=1.0, out=out)
+    torch.cuda.synchronize()
+    for l in range(len(factors)):
+        pl = {k: v for k, v in pyr.level(l).profile_stop().items() if v["count"]}
+        per_level[l]["attempt_us"] = round(sum(v["avg_ms"] for v in pl.values()) * 1e3, 2)
+        per_level[l]["kernel_us"] = {k: round(v["avg_ms"] * 1e3, 2) for k, v in pl.items()}
     elapsed = t1 - t0
     nfine = int(np.prod(shape))
     kb = kernel_bytes(s)
@@ -488,6 +502,95 @@ def run_batch(a):
     return "f32", value, elapsed, config, roofline, cpu, detail
 
 
+SMALL_SHAPE = (48, 48, 48)
+SMALL_PAIRS = 64
+SMALL_ITERS = 50
+
+
+def run_small(a):
+    """Many small pairs, where one pair's kernels leave most of the GPU idle:
+    64 brain-like 48^3 pairs, 50 LM attempts each at full resolution.  The
+    batched persistent form (one launch per attempt for all pairs) against
+    the same pairs run as stand-alone contexts (one HIP graph of 50 attempts
+    per pair), one after another and spread over four streams."""
+    import numpy as np
+    import torch
+    from paper_2603_19371_amd import _lib, phantoms_torch
+
+    shapes = [SMALL_SHAPE] * SMALL_PAIRS
+    pairs = [phantoms_torch.brain(SMALL_SHAPE, seed=300 + i) for i in range(SMALL_PAIRS)]
+    Fs = [p[0] for p in pairs]
+    Ms = [p[1] for p in pairs]
+    nvox = int(np.prod(SMALL_SHAPE))
+    kw = dict(window=WINDOW, grad_sigma=SIGMA, accum=ACCUM[a.accum])
+
+    b = _lib.Batch(shapes, **kw)
+    import tempfile
+    cache = os.environ.get("LMR_TUNE_CACHE",
+                           os.path.join(tempfile.gettempdir(), "lmr_batch_tune.txt"))
+    # attempts of small pairs take about a millisecond: ten per trial keep
+    # the tuner's choice above its timing noise
+    b.tune(Fs, Ms, cache_path=cache, iters=10)
+    for _ in range(a.warmup):
+        b.begin(Fs, Ms)
+        b.step(SMALL_ITERS, graph=True)
+        b.sync()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        b.begin(Fs, Ms)
+        b.step(SMALL_ITERS, graph=True)
+    b.sync()
+    elapsed = time.perf_counter() - t0
+    attempts = [b.pair(i).state()["attempts"] for i in range(SMALL_PAIRS)]
+    vox_att = nvox * sum(attempts)
+    value = vox_att * a.steps / elapsed
+
+    # the same pairs as stand-alone contexts: a one-level pyramid per pair
+    # replays its 50 attempts as one HIP graph
+    def per_pair(nstreams):
+        streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        pyrs = [_lib.Pyramid(SMALL_SHAPE, (1,), stream=streams[i % nstreams], **kw)
+                for i in range(SMALL_PAIRS)]
+        outs = [torch.empty((3,) + SMALL_SHAPE, device="cuda") for _ in range(SMALL_PAIRS)]
+        torch.cuda.synchronize()
+
+        def once():
+            for i, pyr in enumerate(pyrs):
+                pyr.run(Fs[i], Ms[i], [SMALL_ITERS], lambda0=1.0, out=outs[i])
+        for _ in range(max(1, a.warmup)):
+            once()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(a.steps):
+            once()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        n = nvox * sum(int(pyr.level(0).state()["attempts"]) for pyr in pyrs)
+        return n * a.steps / dt, dt / a.steps * 1e3
+
+    seq_v, seq_ms = per_pair(1)
+    par_v, par_ms = per_pair(4)
+    per_attempt_s = elapsed / (a.steps * SMALL_ITERS)
+    achieved = attempt_bytes(4) * nvox * SMALL_PAIRS / per_attempt_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "batch_attempt (one persistent launch per attempt)",
+                "algorithmic_bytes_per_launch": attempt_bytes(4) * nvox * SMALL_PAIRS,
+                "mean_launch_ms": round(per_attempt_s * 1e3, 5),
+                "launches_timed": a.steps * SMALL_ITERS}
+    config = {"workload": f"{SMALL_PAIRS} brain-like pairs of 48^3, FP32, LNCC w=7, "
+                          f"sigma_g=1, {SMALL_ITERS} attempts at full resolution, batched "
+                          "persistent form (one launch per attempt, HIP graph, autotuned)",
+              "pairs": SMALL_PAIRS, "voxel_attempts_per_step": vox_att}
+    detail = {"batched_ms_per_run": round(elapsed / a.steps * 1e3, 3),
+              "per_pair_sequential": {"value": round(seq_v, 1), "ms_per_run": round(seq_ms, 3)},
+              "per_pair_4_streams": {"value": round(par_v, 1), "ms_per_run": round(par_ms, 3)},
+              "batched_speedup_vs_sequential": round(value / seq_v, 3),
+              "batched_speedup_vs_4_streams": round(value / par_v, 3),
+              "tuned_config": b.config(), "kernel_source_sha": source_sha()}
+    return "f32", value, elapsed, config, roofline, None, detail
+
+
 def unet_flops(shape):
     """Multiply-add FLOPs (2 per MAC) of the network's 15 convolutions at
     `shape` (its own resolution): forward, and forward + backward (input
@@ -571,7 +674,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="brain workload: skip the learned-initializer and 384^3 legs")
-    ap.add_argument("--workload", choices=("brain", "lung", "abdomen", "batch", "unet"),
+    ap.add_argument("--workload",
+                    choices=("brain", "lung", "abdomen", "batch", "small", "unet"),
                     default="brain")
     ap.add_argument("--accum", choices=tuple(ACCUM), default="f64",
                     help="box-sum accumulator of the LNCC passes")
@@ -582,10 +686,11 @@ def main():
         sys.exit(2)
 
     run = {"brain": run_brain, "lung": run_lung, "abdomen": run_abdomen,
-           "batch": run_batch, "unet": run_unet}[a.workload]
+           "batch": run_batch, "small": run_small, "unet": run_unet}[a.workload]
     dtype, value, elapsed, config, roofline, cpu, detail = run(a)
     line = {
         "metric": {"batch": "voxel-attempts/s of the LM step (batched pairs)",
+                   "small": "voxel-attempts/s of the LM step (batched pairs)",
                    "unet": "U-Net forward passes/s of the learned initializer"}.get(
                        a.workload,
                        "voxel-attempts/s of the LM step (full coarse-to-fine registration)"),

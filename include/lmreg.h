@@ -55,7 +55,9 @@ typedef enum {
   LMR_ENOMEM = 2,   /* device allocation failed */
   LMR_EHIP = 3,     /* a HIP runtime call failed */
   LMR_ESTATE = 4,   /* call out of order (e.g. lmr_step before lmr_begin) */
-  LMR_ESTALLED = 5  /* the pair is frozen (see lmr_params.max_retries) */
+  LMR_ESTALLED = 5, /* the pair is frozen (see lmr_params.max_retries) */
+  LMR_EBUSY = 6     /* a batched launch could not have all its blocks on the GPU
+                       at once (other work held it): see lmr_batch_sync */
 } lmr_status;
 
 typedef enum { LMR_F32 = 0, LMR_BF16 = 1 } lmr_dtype;
@@ -352,13 +354,19 @@ void lmr_pyramid_destroy(lmr_pyramid* pyr);
  * results of one pair are read through lmr_batch_pair (borrowed context).
  * Box side 3..9 and Gaussian radius ceil(3 sigma) <= 4 are supported (else
  * LMR_EINVAL).  Its stencils march (LMR_STENCIL_MARCH, whatever p->stencil
- * says), so a pair follows a stand-alone context with that form bit for bit.  A barrier wait longer than 0.25 s (which means the blocks
- * were not all resident) makes every block leave; lmr_batch_sync reports it
- * as LMR_EHIP.  The persistent launch needs all its blocks resident at once:
- * kernels running at the same time on other streams (another batch's steps
- * included) can hold the resources its last blocks wait for, so let such
- * work finish first; a launch that cannot become resident times out as
- * above instead of hanging. */
+ * says), so a pair follows a stand-alone context with that form bit for bit.
+ *
+ * Co-residency.  The persistent launch needs all its blocks on the GPU at
+ * once; the caller must not run other kernels at the same time on other
+ * streams (another batch's steps included) that could hold the resources
+ * some of its blocks need.  Each launch checks this at its first barrier:
+ * when a block has waited there 2 ms while some block of the grid has not
+ * even started, the launch gives up and lmr_batch_sync reports LMR_EBUSY (a
+ * few milliseconds, not a timeout): the pairs keep the state of the last
+ * completed launch, later launches of the same step return at once, and the
+ * batch may be stepped again once the other work is done.  Any barrier wait
+ * longer than 0.25 s also makes every block leave (LMR_EHIP at
+ * lmr_batch_sync).  Neither can hang the device. */
 typedef struct lmr_batch lmr_batch;
 lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes,
                             lmr_dtype img, const lmr_params* p);
@@ -371,8 +379,14 @@ lmr_status lmr_batch_begin(lmr_batch* b, const void* const* fixed,
 /* Enqueues n_iters iterations (one persistent launch each); use_graph = 1
  * replays a captured HIP graph of the n_iters launches. */
 lmr_status lmr_batch_step(lmr_batch* b, int n_iters, int use_graph);
-/* Synchronises the batch stream; LMR_EHIP if a barrier wait timed out. */
+/* Synchronises the batch stream; LMR_EBUSY if a launch was not co-resident,
+ * LMR_EHIP if a barrier wait timed out (both clear, so the batch can go on). */
 lmr_status lmr_batch_sync(lmr_batch* b);
+/* For callers testing their handling of LMR_EBUSY: with late_block = 1, block
+ * 0 of every later launch starts 4 ms late, as a block that was not on the
+ * GPU would, so each launch takes the co-residency failure path above
+ * (0 = normal operation, the default). */
+lmr_status lmr_batch_test_residency(lmr_batch* b, int late_block);
 lmr_ctx* lmr_batch_pair(lmr_batch* b, int i);
 /* Tiling knobs: target tile count per pair, minimum z-chunk, persistent
  * blocks per CU (0 = as many as fit). */

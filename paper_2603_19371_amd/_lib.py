@@ -23,7 +23,8 @@ LIB_PATH = os.path.join(_HERE, "liblmreg.so")
 LMR_F32, LMR_BF16 = 0, 1
 LMR_ACC_F64, LMR_ACC_F32C = 0, 1
 _STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory",
-           3: "HIP runtime error", 4: "call out of order", 5: "pair is frozen"}
+           3: "HIP runtime error", 4: "call out of order", 5: "pair is frozen",
+           6: "batched launch not co-resident"}
 
 
 class LmrError(RuntimeError):
@@ -31,6 +32,7 @@ class LmrError(RuntimeError):
 
 
 # lmr_stencil_form
+LMR_EBUSY = 6
 LMR_STENCIL_AUTO, LMR_STENCIL_MARCH, LMR_STENCIL_CUBE = 0, 1, 2
 
 
@@ -131,6 +133,7 @@ def lib() -> C.CDLL:
                                      C.POINTER(_D)]),
             "lmr_batch_step": (_I, [_V, _I, _I]),
             "lmr_batch_sync": (_I, [_V]),
+            "lmr_batch_test_residency": (_I, [_V, _I]),
             "lmr_batch_pair": (_V, [_V, _I]),
             "lmr_batch_set_config": (_I, [_V, _I, _I, _I]),
             "lmr_batch_get_config": (_I, [_V, C.POINTER(_I)]),
@@ -173,7 +176,8 @@ def exported_symbols():
             "lmr_profile_stop", "lmr_avgpool", "lmr_upsample_field",
             "lmr_pyramid_create", "lmr_pyramid_run", "lmr_pyramid_level",
             "lmr_pyramid_destroy", "lmr_pyramid_use_graphs", "lmr_folded_count", "lmr_batch_create",
-            "lmr_batch_begin", "lmr_batch_step", "lmr_batch_sync", "lmr_batch_pair",
+            "lmr_batch_begin", "lmr_batch_step", "lmr_batch_sync",
+            "lmr_batch_test_residency", "lmr_batch_pair",
             "lmr_batch_set_config", "lmr_batch_get_config", "lmr_batch_tune",
             "lmr_batch_destroy", "lmr_unet_param_count", "lmr_unet_layer_info",
             "lmr_unet_create", "lmr_unet_destroy", "lmr_unet_set_params",
@@ -557,6 +561,14 @@ class Batch:
 
     def sync(self):
         _check(lib().lmr_batch_sync(self._h), "lmr_batch_sync")
+
+    def sync_status(self) -> int:
+        """lmr_batch_sync's status (0, or LMR_EBUSY / LMR_EHIP) without raising."""
+        return int(lib().lmr_batch_sync(self._h))
+
+    def test_residency(self, late_block: int):
+        _check(lib().lmr_batch_test_residency(self._h, int(late_block)),
+               "lmr_batch_test_residency")
 
     def tune(self, Fs, Ms, cache_path=None, iters=3):
         fp, mp = self._ptrs(Fs, Ms)

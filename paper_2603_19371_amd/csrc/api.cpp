@@ -168,6 +168,7 @@ const char* lmr_strerror(lmr_status s) {
     case LMR_EHIP: return "HIP runtime error";
     case LMR_ESTATE: return "call out of order";
     case LMR_ESTALLED: return "pair is frozen";
+    case LMR_EBUSY: return "batched launch not co-resident (GPU held by other work)";
   }
   return "unknown status";
 }

@@ -36,6 +36,8 @@ struct lmr_batch {
   int target_tiles = 2048, min_cz = 16, blocks_per_cu = 0;
   int n_update_items = 0, n_tiles = 0;
   unsigned long long timeout = 0;  // barrier timeout in wall-clock ticks
+  unsigned long long start_timeout = 0;  // co-residency check, wall-clock ticks
+  int missing = 0;                       // test hook (lmr_batch_test_residency)
   std::map<int, hipGraphExec_t> graphs;  // n_iters -> instantiated graph
   bool begun = false;
 };
@@ -87,7 +89,8 @@ lmr_status enqueue_steps(lmr_batch* b, int n) {
   const int grid = grid_of(b);
   for (int i = 0; i < n; ++i)
     LMR_HIP(launch_batch_attempt(b->kernel, grid, b->dev_pairs, b->npairs, b->n_update_items,
-                                 b->n_tiles, b->ctl, b->dp, b->timeout, b->stream));
+                                 b->n_tiles, b->ctl, b->dp, b->timeout, b->start_timeout,
+                                 b->missing, b->stream));
   return LMR_OK;
 }
 
@@ -157,6 +160,10 @@ lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes, lmr_
       wall_khz <= 0)
     wall_khz = 100000;
   b->timeout = (unsigned long long)wall_khz * 250;  // 0.25 s per barrier wait
+  // blocks of one launch start within microseconds of each other when the
+  // GPU is free: 2 ms at the first barrier with some block not started means
+  // the grid is not co-resident
+  b->start_timeout = (unsigned long long)wall_khz * 2;
   float taps[16] = {0};
   {
     const int R = rg;
@@ -264,8 +271,15 @@ lmr_status lmr_batch_sync(lmr_batch* b) {
   if (h.error.v) {
     // clear the flag so that the batch can be used again
     LMR_HIP(hipMemset(b->ctl, 0, sizeof(BatchCtl)));
-    return LMR_EHIP;
+    return h.error.v == 2 ? LMR_EBUSY : LMR_EHIP;
   }
+  return LMR_OK;
+}
+
+lmr_status lmr_batch_test_residency(lmr_batch* b, int late_block) {
+  if (!b || late_block < 0 || late_block > 1) return LMR_EINVAL;
+  b->missing = late_block;
+  drop_graphs(b);  // captured launches hold the old value
   return LMR_OK;
 }
 

@@ -35,9 +35,15 @@ static_assert(kBatchUpdateTX == kSX && kBatchUpdateTY == kSY && kNT == kSNT,
 
 // Grid-wide barrier among `nblocks` co-resident blocks (two-level arrival on
 // monotonic counters, see BatchCtl).  A wait longer than `timeout` ticks of
-// the device's constant-rate wall clock records an error.  Returns false when
-// this wait timed out or another block reported one.
-__device__ bool grid_sync(BatchCtl* ctl, unsigned nblocks, unsigned long long timeout) {
+// the device's constant-rate wall clock records error 1.  With
+// expect_started > 0 (the first barrier of a launch), a wait longer than
+// start_timeout ticks while fewer than expect_started blocks have started
+// records error 2: some block of the grid is not on the GPU (other work holds
+// its resources), so waiting longer would only wait for that work.  Returns
+// false when this wait failed or another block reported a failure.
+__device__ bool grid_sync(BatchCtl* ctl, unsigned nblocks, unsigned long long timeout,
+                          unsigned long long expect_started = 0,
+                          unsigned long long start_timeout = 0) {
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -64,10 +70,21 @@ __device__ bool grid_sync(BatchCtl* ctl, unsigned nblocks, unsigned long long ti
       // under the working blocks every time); the fence below acquires once
       while (__hip_atomic_load(&ctl->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <=
              epoch) {
-        if (wall_clock64() - t0 > timeout ||
-            __hip_atomic_load(&ctl->error.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        const unsigned long long dt = wall_clock64() - t0;
+        unsigned long long code = 0;
+        if (dt > timeout)
+          code = 1;
+        else if (expect_started && dt > start_timeout &&
+                 __hip_atomic_load(&ctl->started.v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) < expect_started)
+          code = 2;
+        if (code) {
           good = 0;
-          atomicExch(&ctl->error.v, 1ull);
+          atomicCAS(&ctl->error.v, 0ull, code);  // the first failure is reported
+          break;
+        }
+        if (__hip_atomic_load(&ctl->error.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          good = 0;
           break;
         }
         __builtin_amdgcn_s_sleep(4);
@@ -102,7 +119,8 @@ template <int RB, int RG, typename T, typename Acc>
 __global__ void __launch_bounds__(kNT)
     k_batch_attempt(const BatchPair* __restrict__ pairs, int npairs, int n_update_items,
                     int n_tiles, BatchCtl* ctl, DecideParams dp,
-                    unsigned long long timeout) {
+                    unsigned long long timeout, unsigned long long start_timeout,
+                    int missing) {
   const int nb = gridDim.x;
   // the phases are separated by grid barriers, so their LDS is overlaid
   __shared__ union {
@@ -111,8 +129,21 @@ __global__ void __launch_bounds__(kNT)
     StencilLds<RB, kTY, BwdPol<T, Acc>> bwd;
     StencilLds<RG, kTY, SmoothPol<RG>> smo;
   } lds;
-  // after a barrier timeout every later launch returns at once
+  // after a barrier failure every later launch returns at once
   if (__hip_atomic_load(&ctl->error.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  // count this block in; launches of one stream do not overlap, so the
+  // ticket tells the launch and how many blocks must have started with it
+  __shared__ unsigned long long expect;
+  if (threadIdx.x == 0) {
+    if (missing && blockIdx.x == 0) {
+      // test hook: this block starts twice the co-residency limit late, as
+      // a block that was not on the GPU would (bounded wait)
+      const unsigned long long t0 = wall_clock64();
+      while (wall_clock64() - t0 < 2 * start_timeout) __builtin_amdgcn_s_sleep(8);
+    }
+    const unsigned long long ticket = atomicAdd(&ctl->started.v, 1ull);
+    expect = (ticket / nb + 1) * nb;
+  }
 
   // P1: closed form, compositive integration, candidate warp (and its
   // derivative, which P4 reads), one staged tile per work item
@@ -136,7 +167,10 @@ __global__ void __launch_bounds__(kNT)
         for (int z = z0; z < z1; ++z) update_voxel(static_cast<const T*>(P.M), P.g, a, x, y, z);
     }
   }
-  if (!grid_sync(ctl, nb, timeout)) return;
+  // P1 wrote only candidates (the accepted fields, the smoothed gradients
+  // and the states are untouched), so a launch that fails here leaves every
+  // pair as the previous launch left it
+  if (!grid_sync(ctl, nb, timeout, expect, start_timeout)) return;
 
   // P2: LNCC forward, one partial of cc per tile
   for (int it = blockIdx.x; it < n_tiles; it += nb) {

@@ -16,9 +16,10 @@ const void* batch_kernel(lmr_dtype t, lmr_accum accum, int box_radius, int gauss
 hipError_t launch_batch_attempt(const void* kernel, int grid, const BatchPair* pairs,
                                 int npairs, int n_update_items, int n_tiles, BatchCtl* ctl,
                                 const DecideParams& dp, unsigned long long timeout,
+                                unsigned long long start_timeout, int missing,
                                 hipStream_t s) {
-  void* args[] = {&pairs, &npairs, &n_update_items, &n_tiles, &ctl,
-                  const_cast<DecideParams*>(&dp), &timeout};
+  void* args[] = {&pairs,   &npairs,        &n_update_items, &n_tiles, &ctl,
+                  const_cast<DecideParams*>(&dp), &timeout, &start_timeout, &missing};
   return hipLaunchKernel(kernel, dim3(grid), dim3(kNT), args, 0, s);
 }
 

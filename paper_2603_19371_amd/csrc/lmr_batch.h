@@ -53,7 +53,8 @@ struct BatchCtl {
   Line group[kBarGroups];
   Line top;
   Line gen;
-  Line error;
+  Line started;  // blocks that have started, over all launches since the reset
+  Line error;    // 1: a barrier wait timed out, 2: the grid was not co-resident
 };
 
 int batch_tile_rows();
@@ -64,9 +65,14 @@ int batch_block_threads();
 const void* batch_kernel(lmr_dtype t, lmr_accum accum, int box_radius, int gauss_radius);
 // the compensated-FP32 set of the above (k_batch_f32c.hip)
 const void* batch_kernel_f32c(lmr_dtype t, int box_radius, int gauss_radius);
+// timeout: ticks of a barrier wait; start_timeout: ticks after which a
+// block waiting at the first barrier of a launch gives up if some block of
+// the grid has not started; missing: 0, or 1 to make block 0 of every launch
+// start 2 start_timeout late (exercises the co-residency failure).
 hipError_t launch_batch_attempt(const void* kernel, int grid, const BatchPair* pairs,
                                 int npairs, int n_update_items, int n_tiles, BatchCtl* ctl,
                                 const DecideParams& dp, unsigned long long timeout,
+                                unsigned long long start_timeout, int missing,
                                 hipStream_t s);
 
 }  // namespace lmr

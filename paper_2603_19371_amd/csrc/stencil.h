@@ -306,15 +306,39 @@ __device__ __forceinline__ void stencil_cube(const P& pol, const Geom& g, int x0
                              : kFarIndex;
       pol.load(loc, i, r[k]);
     }
-#pragma unroll
-    for (int oz = 0; oz < kT3; ++oz) {
+    if constexpr (P::kBox) {
+      // running sum down the column: the entering position's terms are
+      // added, the leaving position's (formed again) subtracted
       A a[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) a[c] = A();
 #pragma unroll
-      for (int k = 0; k < W; ++k) pol.accum(a, r[oz + k], k);
+      for (int k = 0; k < W; ++k) pol.accum(a, r[k], k);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) sm.z[c][oz][yy][xx] = a[c];
+      for (int oz = 0; oz < kT3; ++oz) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sm.z[c][oz][yy][xx] = a[c];
+        if (oz + 1 < kT3) {
+          A in_[NC], out_[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) in_[c] = out_[c] = A();
+          pol.accum(in_, r[oz + W], 0);
+          pol.accum(out_, r[oz], 0);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) a[c] += in_[c] - out_[c];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int oz = 0; oz < kT3; ++oz) {
+        A a[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) a[c] = A();
+#pragma unroll
+        for (int k = 0; k < W; ++k) pol.accum(a, r[oz + k], k);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sm.z[c][oz][yy][xx] = a[c];
+      }
     }
   }
   __syncthreads();

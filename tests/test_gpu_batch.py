@@ -1,6 +1,7 @@
 """Batched persistent form: equivalence with per-pair runs and graph replays,
 and parity with the FP64 oracle at the shapes of the 16-pair workload."""
 import os
+import time
 
 import numpy as np
 import pytest
@@ -93,6 +94,42 @@ def test_graph_replays_match_eager_steps(L, pairs):
             assert graph.pair(i).state() == eager.pair(i).state(), (rep, i)
             assert np.array_equal(host(graph.pair(i).field()),
                                   host(eager.pair(i).field())), (rep, i)
+
+
+def test_launch_not_co_resident_fails_fast(L, pairs):
+    """A launch whose grid is not all on the GPU gives up at its first barrier
+    within milliseconds (LMR_EBUSY, not the 0.25 s barrier timeout), leaves
+    every pair as the last completed launch left it, and the batch steps on
+    afterwards.  The absent block is simulated (lmr_batch_test_residency:
+    block 0 starts 4 ms late): the GPU is never actually contended, and every
+    wait of the kernel is bounded."""
+    Fs, Ms = [F for F, _ in pairs], [M for _, M in pairs]
+    b = L.Batch(SHAPES, window=5)
+    b.begin(Fs, Ms)
+    b.step(2, graph=False)
+    b.sync()
+    before = [(host(b.pair(i).field()), b.pair(i).state()) for i in range(len(SHAPES))]
+    b.test_residency(1)
+    t0 = time.perf_counter()
+    b.step(3, graph=False)
+    status = b.sync_status()
+    dt = time.perf_counter() - t0
+    print(f"[co-residency] status={status} after {dt * 1e3:.2f} ms", flush=True)
+    assert status == L.LMR_EBUSY
+    assert dt < 0.1, dt
+    for i, (u, st) in enumerate(before):
+        assert b.pair(i).state() == st, i
+        assert np.array_equal(host(b.pair(i).field()), u), i
+    b.test_residency(0)
+    b.step(2, graph=True)
+    assert b.sync_status() == 0
+    ref = L.Batch(SHAPES, window=5)
+    ref.begin(Fs, Ms)
+    ref.step(4, graph=False)
+    ref.sync()
+    for i in range(len(SHAPES)):
+        assert b.pair(i).state() == ref.pair(i).state(), i
+        assert np.array_equal(host(b.pair(i).field()), host(ref.pair(i).field())), i
 
 
 def test_autotuner_and_cache(L, pairs, tmp_path):
