@@ -10,6 +10,10 @@ kernel-trace durations per kernel and grid size.
         --name update --workload brain160x192x224_f32_w7 --command "..." \\
         [--out profiles/update__brain160x192x224_f32_w7.pmc.txt]
 
+    python -m paper_2603_19371_amd.pmc_summary sq --csv C.csv \\
+        --workload unet80x96x112 --command "..." --kernels k_conv_tile,k_wgrad \\
+        --out profiles/sq__unet80x96x112.txt
+
 Inputs are the counter-collection CSV files of four rocprofv3 --pmc runs: the
 workload with FETCH_SIZE, the workload with WRITE_SIZE, and the reference copy
 (paper_2603_19371_amd.calib) with each counter.  FETCH_SIZE and WRITE_SIZE
@@ -135,6 +139,41 @@ def trace_summary(a):
     print("\n".join(lines))
 
 
+def sq_summary(a):
+    """Per (kernel, grid): dispatches and the mean per dispatch of each
+    counter of one --pmc pass; SQ_ instruction and cycle counters also per
+    wave (divided by SQ_WAVES of the same dispatches)."""
+    per = {}
+    for r in _rows(a.csv):
+        name = _short(r.get("Kernel_Name", ""))
+        if a.kernels and not any(k in name for k in a.kernels.split(",")):
+            continue
+        grid = int(float(r.get("Grid_Size", "0")))
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        d = per.setdefault((name, grid), {}).setdefault(key, {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    lines = [f"# rocprofv3 --pmc counters per dispatch, workload {a.workload}",
+             f"# command: {a.command}",
+             "# kernel | grid (work-items) | dispatches | counter = mean per dispatch "
+             "(per wave)"]
+    for (name, grid), disp in sorted(per.items(), key=lambda kv: (kv[0][0], -kv[0][1])):
+        names = sorted({c for d in disp.values() for c in d})
+        mean = {c: statistics.mean(d.get(c, 0.0) for d in disp.values()) for c in names}
+        waves = mean.get("SQ_WAVES")
+        cells = []
+        for c in names:
+            cell = f"{c}={mean[c]:.4g}"
+            if waves and c != "SQ_WAVES" and c.startswith(("SQ_INSTS", "SQ_LDS", "SQ_WAIT",
+                                                           "SQ_WAVE_CYCLES")):
+                cell += f" ({mean[c] / waves:.1f}/wave)"
+            cells.append(cell)
+        lines.append(f"{name} | {grid} | {len(disp)} | " + "; ".join(cells))
+    out = a.out
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -150,9 +189,16 @@ def main():
     c.add_argument("--copy-bytes", type=int, required=True)
     c.add_argument("--grid", type=int, required=True)
     c.add_argument("--out")
+    q = sub.add_parser("sq")
+    for k in ("csv", "workload", "command", "out"):
+        q.add_argument("--" + k, required=True)
+    q.add_argument("--kernels", default="", help="comma-separated name fragments")
     a = ap.parse_args()
     if a.cmd == "trace":
         trace_summary(a)
+        return
+    if a.cmd == "sq":
+        sq_summary(a)
         return
     f_kib, nf = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel, a.grid)
     w_kib, nw = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel, a.grid)
