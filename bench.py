@@ -23,12 +23,14 @@ Printed on one JSON line, with
                 same workload (attempts at the full-resolution level, at the
                 host's thread count and at one thread; the whole 50-attempt run
                 of the 32^3 blob pair), with the CPU model;
-  detail        per-level attempts and losses; for the brain workload also the
-                learned initializer's time to the plain method's final LNCC on
-                16 held-out seeds, the attempt time at 384^3 with BF16 images,
-                and device memory and time per iteration of the LM step and of
-                the Adam comparator on N^3 volumes, N = 64..512 (--no-extra
-                skips these).
+  detail        per-level attempts and losses, and the wall time of one attempt
+                at each level (the level's pooled pair alone, replayed from a
+                HIP graph); for the brain workload also the learned
+                initializer's time to the plain method's final LNCC on 16
+                held-out seeds, the attempt time at 384^3 with BF16 images, and
+                device memory and time per iteration of the LM step and of the
+                Adam comparator on N^3 volumes, N = 64..512 (--no-extra skips
+                the per-level times and these).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                     [--workload brain|lung|abdomen|batch|small|unet] [--accum f64|f32c]
@@ -174,6 +176,37 @@ def cpu_baseline(F, M, attempts=2, what="the full-resolution level", single_thre
     return out
 
 
+def level_attempt_us(F, M, factor, n, img_dtype, a):
+    """Mean wall time of one attempt of a pyramid level: the pair average-
+    pooled by `factor`, n attempts as one graph replay, minus one attempt."""
+    import torch
+    import torch.nn.functional as tf
+    from paper_2603_19371_amd import _lib
+
+    def pool(x):
+        x = x.float()
+        if factor > 1:
+            x = tf.avg_pool3d(x[None, None], factor)[0, 0]
+        return x.to(img_dtype).contiguous()
+    Fl, Ml = pool(F), pool(M)
+    shape = tuple(Fl.shape)
+    pyr = _lib.Pyramid(shape, (1,), img_dtype=img_dtype, window=WINDOW, grad_sigma=SIGMA,
+                       accum=ACCUM[a.accum])
+    out = torch.empty((3,) + shape, device="cuda")
+    ms = {}
+    for k in (1, n):
+        for _ in range(2):
+            pyr.run(Fl, Ml, [k], lambda0=1.0, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 10
+        for _ in range(reps):
+            pyr.run(Fl, Ml, [k], lambda0=1.0, out=out)
+        torch.cuda.synchronize()
+        ms[k] = (time.perf_counter() - t0) / reps * 1e3
+    return (ms[n] - ms[1]) / (n - 1) * 1e3
+
+
 def _pyramid_line(a, F, M, img_dtype, factors, iters, workload, s):
     """Times `steps` full coarse-to-fine registrations; roofline from the
     fine level's kernel events."""
@@ -206,17 +239,14 @@ def _pyramid_line(a, F, M, img_dtype, factors, iters, workload, s):
         per_level.append({"factor": f, "voxels": n, "attempts": int(st["attempts"]),
                           "accepted_loss": st["loss"], "lambda": st["lambda_"]})
         vox_att += n * int(st["attempts"])
-    # mean kernel times per attempt at every level: one more registration
-    # outside the timed region with every level's kernels timed (a timed
-    # level runs its attempts eagerly rather than as a graph replay)
-    for l in range(len(factors)):
-        pyr.level(l).profile_start(max_attempts=iters[l], stride=1)
-    pyr.run(F, M, iters, lambda0=1.0, out=out)
-    torch.cuda.synchronize()
-    for l in range(len(factors)):
-        pl = {k: v for k, v in pyr.level(l).profile_stop().items() if v["count"]}
-        per_level[l]["attempt_us"] = round(sum(v["avg_ms"] for v in pl.values()) * 1e3, 2)
-        per_level[l]["kernel_us"] = {k: round(v["avg_ms"] * 1e3, 2) for k, v in pl.items()}
+    # wall time per attempt at every level, outside the timed region: each
+    # level's pooled pair alone as a one-level registration replayed from a
+    # HIP graph, (T(n attempts) - T(1 attempt)) / (n - 1), which leaves out
+    # the level's begin
+    if not a.no_extra:
+        for l, f in enumerate(factors):
+            per_level[l]["attempt_us"] = round(
+                level_attempt_us(F, M, f, iters[l], img_dtype, a), 2)
     elapsed = t1 - t0
     nfine = int(np.prod(shape))
     kb = kernel_bytes(s)
@@ -673,7 +703,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="brain workload: skip the learned-initializer and 384^3 legs")
+                    help="skip the per-level attempt times and, for the brain workload, "
+                         "the learned-initializer, 384^3 and Adam legs")
     ap.add_argument("--workload",
                     choices=("brain", "lung", "abdomen", "batch", "small", "unet"),
                     default="brain")

@@ -35,14 +35,30 @@ static_assert(kBatchUpdateTX == kSX && kBatchUpdateTY == kSY && kNT == kSNT,
 
 // Grid-wide barrier among `nblocks` co-resident blocks (two-level arrival on
 // monotonic counters, see BatchCtl).  A wait longer than `timeout` ticks of
-// the device's constant-rate wall clock records error 1.  With
-// expect_started > 0 (the first barrier of a launch), a wait longer than
-// start_timeout ticks while fewer than expect_started blocks have started
-// records error 2: some block of the grid is not on the GPU (other work holds
-// its resources), so waiting longer would only wait for that work.  Returns
-// false when this wait failed or another block reported a failure.
+// the device's constant-rate wall clock records error 1.  With ticket > 0
+// (at the first barrier of a launch: 1 + the block's ticket from count_in),
+// a wait longer than start_timeout ticks while some block of this launch has
+// not even started records error 2: that block is not on the GPU (other work
+// holds its resources), so waiting longer would only wait for that work.
+// The started counts are kept per group like the arrivals, so that the
+// blocks' start does not queue on one cache line.  Returns false when this
+// wait failed or another block reported a failure.
+__device__ __noinline__ bool all_started(BatchCtl* ctl, unsigned nblocks,
+                                         unsigned long long ticket) {
+  // this block's launch (1, 2, ... since the reset) from its ticket
+  const unsigned grp = blockIdx.x % kBarGroups;
+  const unsigned long long launch =
+      ticket / ((nblocks + kBarGroups - 1 - grp) / kBarGroups) + 1;
+  for (int g = 0; g < kBarGroups; ++g) {
+    const unsigned long long in_g = (nblocks + kBarGroups - 1 - g) / kBarGroups;
+    if (in_g && __hip_atomic_load(&ctl->started[g].v, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT) < launch * in_g)
+      return false;
+  }
+  return true;
+}
 __device__ bool grid_sync(BatchCtl* ctl, unsigned nblocks, unsigned long long timeout,
-                          unsigned long long expect_started = 0,
+                          unsigned long long ticket = 0,
                           unsigned long long start_timeout = 0) {
   __shared__ int ok;
   __syncthreads();
@@ -74,9 +90,7 @@ __device__ bool grid_sync(BatchCtl* ctl, unsigned nblocks, unsigned long long ti
         unsigned long long code = 0;
         if (dt > timeout)
           code = 1;
-        else if (expect_started && dt > start_timeout &&
-                 __hip_atomic_load(&ctl->started.v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT) < expect_started)
+        else if (ticket && dt > start_timeout && !all_started(ctl, nblocks, ticket - 1))
           code = 2;
         if (code) {
           good = 0;
@@ -98,6 +112,20 @@ __device__ bool grid_sync(BatchCtl* ctl, unsigned nblocks, unsigned long long ti
   }
   __syncthreads();
   return ok != 0;
+}
+
+// Counts the calling block in on its group's started line and returns its
+// ticket (kept out of line: inlined at the kernel's start it raised the
+// register count of every instantiation by 35-70 VGPRs).  Test hook: with
+// late != 0, block 0 first waits twice the co-residency limit, as a block
+// that was not on the GPU would (bounded wait).
+__device__ __noinline__ unsigned long long count_in(BatchCtl* ctl, int late,
+                                                    unsigned long long start_timeout) {
+  if (late && blockIdx.x == 0) {
+    const unsigned long long t0 = wall_clock64();
+    while (wall_clock64() - t0 < 2 * start_timeout) __builtin_amdgcn_s_sleep(8);
+  }
+  return atomicAdd(&ctl->started[blockIdx.x % kBarGroups].v, 1ull);
 }
 
 // A state field written earlier in this launch by another block: read with a
@@ -132,18 +160,9 @@ __global__ void __launch_bounds__(kNT)
   // after a barrier failure every later launch returns at once
   if (__hip_atomic_load(&ctl->error.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   // count this block in; launches of one stream do not overlap, so the
-  // ticket tells the launch and how many blocks must have started with it
-  __shared__ unsigned long long expect;
-  if (threadIdx.x == 0) {
-    if (missing && blockIdx.x == 0) {
-      // test hook: this block starts twice the co-residency limit late, as
-      // a block that was not on the GPU would (bounded wait)
-      const unsigned long long t0 = wall_clock64();
-      while (wall_clock64() - t0 < 2 * start_timeout) __builtin_amdgcn_s_sleep(8);
-    }
-    const unsigned long long ticket = atomicAdd(&ctl->started.v, 1ull);
-    expect = (ticket / nb + 1) * nb;
-  }
+  // ticket tells which launch this is (thread 0 alone uses it)
+  unsigned long long ticket = 0;
+  if (threadIdx.x == 0) ticket = count_in(ctl, missing, start_timeout) + 1;
 
   // P1: closed form, compositive integration, candidate warp (and its
   // derivative, which P4 reads), one staged tile per work item
@@ -170,7 +189,7 @@ __global__ void __launch_bounds__(kNT)
   // P1 wrote only candidates (the accepted fields, the smoothed gradients
   // and the states are untouched), so a launch that fails here leaves every
   // pair as the previous launch left it
-  if (!grid_sync(ctl, nb, timeout, expect, start_timeout)) return;
+  if (!grid_sync(ctl, nb, timeout, ticket, start_timeout)) return;
 
   // P2: LNCC forward, one partial of cc per tile
   for (int it = blockIdx.x; it < n_tiles; it += nb) {

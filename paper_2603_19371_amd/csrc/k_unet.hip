@@ -161,8 +161,17 @@ __global__ void __launch_bounds__(256) k_conv_tile(ConvArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t s_w[kWRows * kPitch];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nco = a.cout_p / (16 * NT);
-  const int x0 = blockIdx.x * kCT, y0 = blockIdx.y * kCT;
-  const int z = blockIdx.z / nco, co0 = (blockIdx.z % nco) * 16 * NT;
+  // tile id: channel tile fastest, then x, y, z; each XCD takes a contiguous
+  // range of ids, so the blocks that read an input plane (those of output
+  // planes z-1, z, z+1, and every channel tile) mostly share one L2
+  const int tiles_x = (a.nx + kCT - 1) / kCT, tiles_y = (a.ny + kCT - 1) / kCT;
+  int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int co0 = (b % nco) * 16 * NT;
+  b /= nco;
+  const int x0 = (b % tiles_x) * kCT;
+  b /= tiles_x;
+  const int y0 = (b % tiles_y) * kCT;
+  const int z = b / tiles_y;
   const int m = lane & 15, kq = lane >> 4;
   const int q = tid & 3;  // the quad (4 channels) this thread stages
   // ---- input staging: element offsets of this thread's 18 items (chunk 0)
@@ -802,7 +811,9 @@ hipError_t unet_conv(const ConvArgs& a, hipStream_t s) {
     // 32 output channels per block where the layer has them: each input
     // operand read from LDS then feeds two MFMAs
     const int nt = a.cout_p % 32 == 0 ? 2 : 1;
-    dim3 grid((a.nx + kCT - 1) / kCT, (a.ny + kCT - 1) / kCT, a.nz * (a.cout_p / (16 * nt)));
+    const long long nb = (long long)((a.nx + kCT - 1) / kCT) * ((a.ny + kCT - 1) / kCT) *
+                         a.nz * (a.cout_p / (16 * nt));
+    const dim3 grid(static_cast<unsigned>(nb));
     if (nt == 2)
       hipLaunchKernelGGL(k_conv_tile<2>, grid, dim3(256), 0, s, a);
     else

@@ -53,7 +53,8 @@ struct BatchCtl {
   Line group[kBarGroups];
   Line top;
   Line gen;
-  Line started;  // blocks that have started, over all launches since the reset
+  Line started[kBarGroups];  // blocks that have started (per group, as the
+                             // arrivals), over all launches since the reset
   Line error;    // 1: a barrier wait timed out, 2: the grid was not co-resident
 };
 
