@@ -29,8 +29,9 @@ Printed on one JSON line, with
                 initializer's time to the plain method's final LNCC on 16
                 held-out seeds, the attempt time at 384^3 with BF16 images, and
                 device memory and time per iteration of the LM step and of the
-                Adam comparator on N^3 volumes, N = 64..512 (--no-extra skips
-                the per-level times and these).
+                Adam comparator on N^3 volumes, N = 64..512, and short runs of
+                the lung, abdomen, 16-pair and small-pairs workloads below
+                (--no-extra skips the per-level times and these).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                     [--workload brain|lung|abdomen|batch|small|unet] [--accum f64|f32c]
@@ -411,15 +412,49 @@ def run_brain(a):
     value, elapsed, vox_att, roofline, detail = _pyramid_line(
         a, F, M, torch.float32, FACTORS, ITERS, workload, 4)
     if not a.no_extra:
+        progress("learned initializer on held-out seeds")
         detail["learned_init"] = learned_detail()
+        progress("384^3 attempt")
         detail["attempt_384_bf16"] = attempt_detail()
+        progress("LM vs Adam memory and time")
         detail["adam_vs_lm"] = adam_vs_lm_detail()
+        detail["other_workloads"] = other_workloads(a)
     cpu = None if a.no_cpu_baseline else cpu_baseline(ph.F, ph.M)
     config = {"workload": "brain-MRI-like phantom 160x192x224, FP32 images and field, "
                           f"{ACCUM_TEXT[a.accum]}, LNCC w=7, sigma_g=1, pyramid 4x/2x/1x "
                           "with 200/100/50 attempts, lambda0=1, x2/x0.5, tau=0",
               "pairs": 1, "voxel_attempts_per_step": vox_att}
     return "f32", value, elapsed, config, roofline, cpu, detail
+
+
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def other_workloads(a):
+    """The lung, abdomen, 16-pair and many-small-pairs workloads in short runs
+    (1 warm-up and 2 timed steps each, no CPU baseline), so that one default
+    run carries their figures too."""
+    import argparse as _ap
+    out = {}
+    for name, fn in (("lung", run_lung), ("abdomen", run_abdomen), ("batch", run_batch),
+                     ("small", run_small)):
+        progress(f"{name} workload")
+        b = _ap.Namespace(**vars(a))
+        b.steps, b.warmup, b.no_cpu_baseline, b.no_extra = 2, 1, True, True
+        t0 = time.perf_counter()
+        dtype, value, elapsed, config, roofline, _, det = fn(b)
+        e = {"value": round(value, 1), "ms_per_step": round(elapsed / b.steps * 1e3, 3),
+             "dtype": dtype, "workload": config["workload"],
+             "attempt_ms": roofline.get("mean_launch_ms"), "frac": roofline.get("frac"),
+             "wall_s": round(time.perf_counter() - t0, 1)}
+        for k in ("batched_speedup_vs_sequential", "batched_speedup_vs_4_streams",
+                  "per_pair_sequential", "per_pair_4_streams"):
+            if k in det:
+                e[k] = det[k]
+        out[name] = e
+    return out
 
 
 def run_lung(a):
