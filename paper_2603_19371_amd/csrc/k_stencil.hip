@@ -66,6 +66,10 @@ __global__ void __launch_bounds__(kCubeThreads)
 
 Tiling tiling_of(const Geom& g) { return make_tiling(g.nz, g.ny, g.nx, kTY); }
 
+// The forward policy's block reduction is sized for its block: one policy
+// type serves both forms, so both forms launch blocks of the same size.
+static_assert(kTX * kTY == kCubeThreads, "marching tiles and cubes share FwdPol<T, 256>");
+
 // Volumes of at most this many voxels run on cubes under LMR_STENCIL_AUTO
 // (the half- and quarter-resolution levels of a brain-sized pair).
 constexpr long long kCubeMaxVoxels = 1LL << 20;
