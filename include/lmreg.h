@@ -174,7 +174,9 @@ const char* lmr_strerror(lmr_status s);
 const char* lmr_last_error(void);
 void lmr_default_params(lmr_params* p);
 
-/* Creates a context for volumes of nz*ny*nx voxels with images of type img,
+/* Creates a context for one pair (the state the paper's optimizer keeps per
+ * pair: the field and the scalar damping with its loss history, Sec. 2.2)
+ * for volumes of nz*ny*nx voxels with images of type img,
  * bound to `stream` (0 = the null stream).  Allocates the whole workspace
  * (about 80 bytes per voxel: field ping-pong, smoothed gradient, raw
  * gradient, four LNCC adjoint maps, warped image, reduction partials and the
@@ -187,7 +189,8 @@ void lmr_destroy(lmr_ctx* ctx);
 
 /* Starts a registration from `field` (device, [3][nz][ny][nx] FP32; NULL =
  * identity u = 0) with damping lambda0 > 0: evaluates L(u) and the smoothed
- * gradient of u.  fixed/moving: device images of the context's type.  The
+ * gradient of u (the Eulerian descent direction, Sec. 2.1; the residual
+ * r = 1 - LNCC of Sec. 2.2).  fixed/moving: device images of the context's type.  The
  * window mean and variance of `fixed`, which no attempt changes, are computed
  * here once and kept in the context. */
 lmr_status lmr_begin(lmr_ctx* ctx, const void* fixed, const void* moving,
@@ -211,15 +214,24 @@ lmr_status lmr_step(lmr_ctx* ctx, const void* fixed, const void* moving,
  * keeps every step: a forced rejection gives LMR_EINVAL. */
 lmr_status lmr_step_forced(lmr_ctx* ctx, const void* fixed, const void* moving,
                            const int* decisions, int n);
+/* Forces the decision of every later lmr_step attempt (1 accept, 0 reject,
+ * -1 automatic, the default) until called again; lambda and the loss history
+ * follow a forced decision as they follow an automatic one (Sec. 2.2,
+ * eq. lambda-update; Sec. 3.4, eq. rejection).  LMR_EINVAL for other values,
+ * and for 0 on an Adam context. */
+lmr_status lmr_force_decision(lmr_ctx* ctx, int decision);
 
 /* Bytes of device memory the context holds (its whole workspace). */
 lmr_status lmr_workspace_bytes(const lmr_ctx* ctx, size_t* out);
 
-/* Copies the accepted field into field_out (device, [3][nz][ny][nx]). */
+/* Copies the accepted field u (Sec. 2.1: the displacement of Id + u, voxel
+ * units) into field_out (device, [3][nz][ny][nx]). */
 lmr_status lmr_get_field(lmr_ctx* ctx, float* field_out);
-/* Copies the smoothed gradient of the accepted field into g_out (device). */
+/* Copies the smoothed gradient of the accepted field (Sec. 2.1) into g_out
+ * (device). */
 lmr_status lmr_get_grad(lmr_ctx* ctx, float* g_out);
-/* Synchronises the context's stream and returns the pair state. */
+/* Synchronises the context's stream and returns the pair state (lambda and
+ * the loss history of Sec. 2.2 and Sec. 3.4). */
 lmr_status lmr_get_state(lmr_ctx* ctx, lmr_pair_state* out);
 /* Overwrites the device pair state with `in` (host struct): lambda, the loss
  * history, counters and flags.  With lmr_begin on a saved field this resumes

@@ -133,6 +133,7 @@ def lib() -> C.CDLL:
                                      C.POINTER(_D)]),
             "lmr_batch_step": (_I, [_V, _I, _I]),
             "lmr_batch_sync": (_I, [_V]),
+            "lmr_force_decision": (_I, [_V, _I]),
             "lmr_batch_test_residency": (_I, [_V, _I]),
             "lmr_batch_pair": (_V, [_V, _I]),
             "lmr_batch_set_config": (_I, [_V, _I, _I, _I]),
@@ -176,7 +177,7 @@ def exported_symbols():
             "lmr_profile_stop", "lmr_avgpool", "lmr_upsample_field",
             "lmr_pyramid_create", "lmr_pyramid_run", "lmr_pyramid_level",
             "lmr_pyramid_destroy", "lmr_pyramid_use_graphs", "lmr_folded_count", "lmr_batch_create",
-            "lmr_batch_begin", "lmr_batch_step", "lmr_batch_sync",
+            "lmr_force_decision", "lmr_batch_begin", "lmr_batch_step", "lmr_batch_sync",
             "lmr_batch_test_residency", "lmr_batch_pair",
             "lmr_batch_set_config", "lmr_batch_get_config", "lmr_batch_tune",
             "lmr_batch_destroy", "lmr_unet_param_count", "lmr_unet_layer_info",
@@ -263,6 +264,10 @@ class Context:
         arr = (C.c_int * len(decisions))(*[int(d) for d in decisions])
         _check(lib().lmr_step_forced(self._h, f, m, arr, len(decisions)),
                "lmr_step_forced")
+
+    def force_decision(self, decision: int):
+        """Decision of every later step() attempt: 1, 0, or -1 (automatic)."""
+        _check(lib().lmr_force_decision(self._h, int(decision)), "lmr_force_decision")
 
     def field(self, out=None):
         out = out if out is not None else torch.empty((3,) + self.shape,

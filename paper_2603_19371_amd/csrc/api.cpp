@@ -382,9 +382,16 @@ lmr_status lmr_step(lmr_ctx* c, const void* F, const void* M, int n) {
     if (r != LMR_OK) return r;
   }
   for (int i = 0; i < n; ++i) {
-    lmr_status r = enqueue_attempt(c, F, M, -1);
+    lmr_status r = enqueue_attempt(c, F, M, c->forced);
     if (r != LMR_OK) return r;
   }
+  return LMR_OK;
+}
+
+lmr_status lmr_force_decision(lmr_ctx* c, int decision) {
+  if (!c || decision < -1 || decision > 1) return LMR_EINVAL;
+  if (decision == 0 && c->p.optimizer == LMR_OPT_ADAM) return LMR_EINVAL;
+  c->forced = decision;
   return LMR_OK;
 }
 

@@ -41,6 +41,7 @@ struct lmr_ctx {
   unsigned long long* counter;
   bool begun;
   size_t arena_bytes;  // the whole workspace (lmr_workspace_bytes)
+  int forced = -1;     // lmr_force_decision: the decision of later lmr_step attempts
   // tile_size > 1 (eq. tilen): mean g g^T per tile [tiles][6]
   double* H;
   int tiles[3];  // tiles along x, y, z

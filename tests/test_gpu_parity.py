@@ -507,6 +507,35 @@ def test_compensated_sums_on_long_chunks(L, orc, lung_full):
     assert worst_g < 2e-5 * gmax
 
 
+def test_force_decision_matches_forced_steps(L):
+    """lmr_force_decision (a mode for later lmr_step calls) and lmr_step_forced
+    (decisions per call) give the same attempts, bit for bit; a forced
+    rejection leaves the field and raises lambda by mu+."""
+    ph = _config1(7)
+    Fd, Md = dev(ph.F), dev(ph.M)
+    seq = [1, 0, 0, 1, -1, 1]
+    a = L.Context(ph.F.shape, window=5)
+    a.begin(Fd, Md)
+    a.step_forced(Fd, Md, seq)
+    b = L.Context(ph.F.shape, window=5)
+    b.begin(Fd, Md)
+    for d in seq:
+        before = (host(b.field()), b.state())
+        b.force_decision(d)
+        b.step(Fd, Md, 1)
+        if d == 0:
+            st = b.state()
+            assert np.array_equal(host(b.field()), before[0])
+            assert st["accepted"] == 0
+            lam_max = L.Params.make().lambda_max
+            assert st["lambda_"] == min(before[1]["lambda_"] * 2.0, lam_max)
+    b.force_decision(-1)
+    assert np.array_equal(host(a.field()), host(b.field()))
+    assert a.state() == b.state()
+    with pytest.raises(L.LmrError):
+        b.force_decision(2)
+
+
 def test_checkpoint_resume_is_bitwise(L):
     ph = _config1(5)
     Fd, Md = dev(ph.F), dev(ph.M)
