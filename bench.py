@@ -14,7 +14,13 @@ Printed on one JSON line, with
                 read the persisted smoothed gradient: 56 B per voxel with FP32
                 images, 52 with BF16) / the attempt's mean duration, the sum of
                 the kernels' mean durations measured with HIP events the
-                library records on its own stream inside the timed region;
+                library records on its own stream inside the timed region,
+                around every seventh fine-level attempt (--event-stride; the
+                attempts in between run as graph launches, like the coarse
+                levels; 7 is prime to the 50 fine attempts of a step, so the
+                sample moves by one attempt from step to step and covers
+                accepted and rejected attempts in their own proportion rather
+                than a fixed subset);
                 traffic = HBM bytes per attempt from the committed rocprofv3
                 counter summaries when they were taken on the current kernel
                 sources; per_kernel gives each kernel's own figure against the
@@ -223,7 +229,8 @@ def _pyramid_line(a, F, M, img_dtype, factors, iters, workload, s):
         pyr.run(F, M, iters, lambda0=1.0, out=out)
     torch.cuda.synchronize()
     fine = pyr.level(len(factors) - 1)
-    fine.profile_start(max_attempts=iters[-1] * a.steps, stride=1)
+    fine.profile_start(max_attempts=iters[-1] * a.steps // a.event_stride + 1,
+                       stride=a.event_stride)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
@@ -278,6 +285,7 @@ def _pyramid_line(a, F, M, img_dtype, factors, iters, workload, s):
                 "algorithmic_bytes_per_launch": ab,
                 "mean_launch_ms": round(attempt_ms, 5),
                 "launches_timed": max(v["count"] for v in timed.values()),
+                "events_every": a.event_stride,
                 "dominant_kernel": max(timed, key=lambda k: timed[k]["total_ms"]),
                 "per_kernel": per_kernel}
     detail = {
@@ -743,9 +751,15 @@ def main():
     ap.add_argument("--workload",
                     choices=("brain", "lung", "abdomen", "batch", "small", "unet"),
                     default="brain")
+    ap.add_argument("--event-stride", type=int, default=7,
+                    help="HIP events around the kernels of every n-th fine-level attempt "
+                         "(the attempts between two samples run as one graph launch; "
+                         "1: every attempt, all enqueued kernel by kernel)")
     ap.add_argument("--accum", choices=tuple(ACCUM), default="f64",
                     help="box-sum accumulator of the LNCC passes")
     a = ap.parse_args()
+    if a.event_stride < 1:
+        ap.error("--event-stride must be at least 1")
     if a.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(one pair's registration runs on one device).", file=sys.stderr)

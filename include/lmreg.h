@@ -349,7 +349,10 @@ lmr_status lmr_pyramid_run(lmr_pyramid* pyr, const void* fixed, const void* movi
  * private stream, and replayed on the pyramid's stream; the images must stay
  * at the same addresses for a replay to apply).  enable = 0 enqueues the
  * attempts one kernel at a time instead.  Default: enabled.  Forced decisions
- * and levels whose kernel timing is open always run eagerly. */
+ * run eagerly.  On a level whose kernel timing is open with stride 1 every
+ * attempt runs eagerly; with stride s > 1 the sampled attempts run eagerly
+ * between their events and the s - 1 attempts between two samples as one
+ * graph launch (captured with the profiler off). */
 lmr_status lmr_pyramid_use_graphs(lmr_pyramid* pyr, int enable);
 /* The context of level l (borrowed; valid until lmr_pyramid_destroy). */
 lmr_ctx* lmr_pyramid_level(lmr_pyramid* pyr, int level);

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <new>
 #include <tuple>
@@ -729,6 +730,33 @@ lmr_status step_graph(lmr_pyramid* y, int l, const void* Fl, const void* Ml, int
   return LMR_OK;
 }
 
+// n attempts of level l. Without kernel timing they are one graph launch. With
+// timing every stride-th attempt (stride > 1) runs eagerly between its events
+// and the attempts in between run as graphs, so the timed sequence is the
+// graph sequence but for the sampled attempts.
+lmr_status step_sampled(lmr_pyramid* y, int l, const void* Fl, const void* Ml, int n) {
+  lmr_ctx* c = y->lv[l];
+  Profiler& pr = c->prof;
+  if (!pr.on) return step_graph(y, l, Fl, Ml, n);
+  for (int done = 0; done < n;) {
+    int k = static_cast<int>(pr.stride - pr.seen % pr.stride) % pr.stride;
+    if (k == 0) {
+      lmr_status st = lmr_step(c, Fl, Ml, 1);  // records its events
+      if (st != LMR_OK) return st;
+      ++done;
+      continue;
+    }
+    k = std::min(k, n - done);
+    pr.on = false;  // nothing of the profiler goes into a captured graph
+    lmr_status st = step_graph(y, l, Fl, Ml, k);
+    pr.on = true;
+    if (st != LMR_OK) return st;
+    pr.seen += k;
+    done += k;
+  }
+  return LMR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -839,8 +867,8 @@ lmr_status lmr_pyramid_run(lmr_pyramid* y, const void* F, const void* M,
     if (st != LMR_OK) return st;
     if (d)
       st = lmr_step_forced(c, Fl, Ml, d, iters[l]);
-    else if (y->use_graphs && !c->prof.on && iters[l] > 0)
-      st = step_graph(y, l, Fl, Ml, iters[l]);
+    else if (y->use_graphs && iters[l] > 0 && !(c->prof.on && c->prof.stride == 1))
+      st = step_sampled(y, l, Fl, Ml, iters[l]);
     else
       st = lmr_step(c, Fl, Ml, iters[l]);
     if (st != LMR_OK) return st;

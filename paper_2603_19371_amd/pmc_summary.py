@@ -42,6 +42,10 @@ KERNEL_SOURCES = {
     "lncc_fwd": ["k_stencil.hip", "stencil.h", "lmr_internal.h"],
     "lncc_bwd": ["k_stencil.hip", "stencil.h", "lmr_internal.h"],
     "smooth": ["k_stencil.hip", "stencil.h", "lmr_internal.h"],
+    "conv_tile_level0": ["k_unet.hip", "unet_internal.h", "lmr_internal.h"],
+    "wgrad_level0": ["k_unet.hip", "unet_internal.h", "lmr_internal.h"],
+    "batch_attempt": ["k_batch.hip", "batch_attempt.h", "lmr_batch.h", "stencil.h",
+                      "update.h", "decide.h", "lmr_internal.h"],
 }
 
 

@@ -82,6 +82,32 @@ def test_pyramid_graph_replays_match_eager_runs(L):
         assert [graph.level(l).state() for l in range(3)] == ref_states, rep
 
 
+def test_sampled_kernel_timing_keeps_the_graph_sequence(L):
+    """With kernel timing open at stride 4 on the fine level, the sampled
+    attempts run eagerly between their events and the others as graph
+    launches: the same fields and states bit for bit, and one timed attempt
+    in four (a ragged last chunk included)."""
+    from paper_2603_19371_amd import phantoms
+    ph = phantoms.brain((32, 40, 48), seed=5)
+    F, M = dev(ph.F), dev(ph.M)
+    iters = [6, 4, 11]
+    eager = L.Pyramid(ph.F.shape, (4, 2, 1), window=5)
+    eager.use_graphs(False)
+    ref = host(eager.run(F, M, iters))
+    ref_states = [eager.level(l).state() for l in range(3)]
+    pyr = L.Pyramid(ph.F.shape, (4, 2, 1), window=5)
+    fine = pyr.level(2)
+    fine.profile_start(max_attempts=100, stride=4)
+    for rep in range(2):
+        out = pyr.run(F, M, iters)
+        assert np.array_equal(host(out), ref), rep
+        assert [pyr.level(l).state() for l in range(3)] == ref_states, rep
+    prof = fine.profile_stop()
+    # attempts 0, 4, 8 of the first run; the count goes on across runs
+    # (22 attempts in all: 0, 4, ..., 20)
+    assert all(v["count"] == 6 and v["avg_ms"] > 0 for v in prof.values()), prof
+
+
 @pytest.mark.parametrize("shape", [(9, 10, 11), (20, 37, 70), (1, 16, 24)])
 def test_folded_count_is_bit_exact(L, orc, shape):
     """The count is an integer decided in FP64 with the oracle's operation
