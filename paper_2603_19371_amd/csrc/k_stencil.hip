@@ -47,20 +47,20 @@ __global__ void __launch_bounds__(kTX* TY)
   pol.end_tile(loc, tile);  // partials in tile order, as in the batched form
 }
 
-// The same stencil on kT3^3 cubes (small volumes; stencil.h).
-template <int R, class P>
+// The same stencil on TZ x kT3 x kT3 bricks (small volumes; stencil.h).
+template <int R, class P, int TZ>
 __global__ void __launch_bounds__(kCubeThreads)
     k_cube(const P pol, Geom g, int cubes_x, int cubes_y, const DevState* st, int need) {
   if (st && need) {
     if (st->stalled) return;
     if (need == 2 && !st->accepted) return;
   }
-  __shared__ CubeLds<R, P> sm;
+  __shared__ CubeLds<R, P, TZ> sm;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int x0 = (b % cubes_x) * kT3, y0 = ((b / cubes_x) % cubes_y) * kT3;
-  const int z0 = (b / (cubes_x * cubes_y)) * kT3;
+  const int z0 = (b / (cubes_x * cubes_y)) * TZ;
   typename P::Local loc = pol.begin_block(st);
-  stencil_cube<R>(pol, g, x0, y0, z0, loc, sm);
+  stencil_cube<R, TZ>(pol, g, x0, y0, z0, loc, sm);
   pol.end_tile(loc, b);
 }
 
@@ -79,16 +79,33 @@ bool use_cubes(const Geom& g, const lmr_params& p) {
          (p.stencil == LMR_STENCIL_AUTO && g.N <= kCubeMaxVoxels);
 }
 
+// Bricks are 8 planes deep, or 4 where 8-plane bricks would give fewer than
+// kCubeSplitBelow blocks (the quarter-resolution level): there each block's
+// own latency is the launch's, and halving its work halves that.
+constexpr int kCubeSplitBelow = 512;
+
+int cube_columns(const Geom& g) { return ((g.nx + kT3 - 1) / kT3) * ((g.ny + kT3 - 1) / kT3); }
+
+int cube_tz(const Geom& g) {
+  return cube_columns(g) * ((g.nz + 7) / 8) < kCubeSplitBelow ? 4 : 8;
+}
+
 int cube_count(const Geom& g) {
-  return ((g.nx + kT3 - 1) / kT3) * ((g.ny + kT3 - 1) / kT3) * ((g.nz + kT3 - 1) / kT3);
+  const int tz = cube_tz(g);
+  return cube_columns(g) * ((g.nz + tz - 1) / tz);
 }
 
 template <class P, int R>
 hipError_t run(const P& pol, const Geom& g, bool cubes, const DevState* st, int need,
                hipStream_t s) {
   if (cubes) {
-    hipLaunchKernelGGL((k_cube<R, P>), dim3(cube_count(g)), dim3(kCubeThreads), 0, s, pol, g,
-                       (g.nx + kT3 - 1) / kT3, (g.ny + kT3 - 1) / kT3, st, need);
+    const int cx = (g.nx + kT3 - 1) / kT3, cy = (g.ny + kT3 - 1) / kT3;
+    if (cube_tz(g) == 4)
+      hipLaunchKernelGGL((k_cube<R, P, 4>), dim3(cube_count(g)), dim3(kCubeThreads), 0, s,
+                         pol, g, cx, cy, st, need);
+    else
+      hipLaunchKernelGGL((k_cube<R, P, 8>), dim3(cube_count(g)), dim3(kCubeThreads), 0, s,
+                         pol, g, cx, cy, st, need);
     return hipGetLastError();
   }
   const Tiling t = tiling_of(g);

@@ -271,24 +271,31 @@ __device__ __forceinline__ void stencil_tile(const P& pol, const Geom& g, int x0
 // ------------------------------------------------------------- 3D tiles
 // Small volumes (coarse pyramid levels) have too few 32 x TY columns to fill
 // the GPU, and the plane-serial march of a short chunk is their latency.
-// There a block owns a whole kT3^3 cube of outputs instead: each thread
-// reads one (y, x) column of the (kT3 + 2R)^2 halo straight from memory (all
-// its loads in flight at once) and reduces along z, expanding the raw inputs
-// into the accumulated channels; then the block reduces along y and along x
-// in LDS and emits.  Three steps with two barriers instead of a march.
+// There a block owns a whole TZ x kT3 x kT3 brick of outputs instead: each
+// thread reads one (y, x) column of the (kT3 + 2R)^2 halo straight from
+// memory (all its loads in flight at once) and reduces along z, expanding the
+// raw inputs into the accumulated channels; then the block reduces along y
+// and along x in LDS and emits.  Three steps instead of a march.
 constexpr int kT3 = 8;
 constexpr int kCubeThreads = 256;
 
-template <int R, class P>
+// The z sums of the halo columns.  The y pass reads them, keeps its own
+// (fewer) results in registers and, after a barrier, writes them over the z
+// sums, so one array serves both passes and more blocks fit on a CU.
+template <int R, class P, int TZ>
 struct CubeLds {
-  typename P::Acc z[P::NCH][kT3][kT3 + 2 * R][kT3 + 2 * R];
-  typename P::Acc y[P::NCH][kT3][kT3][kT3 + 2 * R];
+  using A = typename P::Acc;
+  static constexpr int L = kT3 + 2 * R;
+  A z[P::NCH][TZ][L][L];
+  __device__ __forceinline__ A (&y())[P::NCH][TZ][kT3][L] {
+    return *reinterpret_cast<A(*)[P::NCH][TZ][kT3][L]>(&z[0][0][0][0]);
+  }
 };
 
-template <int R, class P>
+template <int R, int TZ, class P>
 __device__ __forceinline__ void stencil_cube(const P& pol, const Geom& g, int x0, int y0,
                                              int z0, typename P::Local& loc,
-                                             CubeLds<R, P>& sm) {
+                                             CubeLds<R, P, TZ>& sm) {
   using A = typename P::Acc;
   constexpr int NR = P::NRAW, NC = P::NCH, W = 2 * R + 1, L = kT3 + 2 * R;
   constexpr int NT = kCubeThreads;
@@ -297,9 +304,9 @@ __device__ __forceinline__ void stencil_cube(const P& pol, const Geom& g, int x0
     const int yy = col / L, xx = col - yy * L;
     const int gy = y0 - R + yy, gx = x0 - R + xx;
     const bool in = (unsigned)gy < (unsigned)g.ny && (unsigned)gx < (unsigned)g.nx;
-    float r[L][NR];
+    float r[TZ + 2 * R][NR];
 #pragma unroll
-    for (int k = 0; k < L; ++k) {
+    for (int k = 0; k < TZ + 2 * R; ++k) {
       const int gz = z0 - R + k;
       const unsigned i = (in && (unsigned)gz < (unsigned)g.nz)
                              ? static_cast<unsigned>((gz * g.ny + gy) * g.nx + gx)
@@ -315,10 +322,10 @@ __device__ __forceinline__ void stencil_cube(const P& pol, const Geom& g, int x0
 #pragma unroll
       for (int k = 0; k < W; ++k) pol.accum(a, r[k], k);
 #pragma unroll
-      for (int oz = 0; oz < kT3; ++oz) {
+      for (int oz = 0; oz < TZ; ++oz) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) sm.z[c][oz][yy][xx] = a[c];
-        if (oz + 1 < kT3) {
+        if (oz + 1 < TZ) {
           A in_[NC], out_[NC];
 #pragma unroll
           for (int c = 0; c < NC; ++c) in_[c] = out_[c] = A();
@@ -330,7 +337,7 @@ __device__ __forceinline__ void stencil_cube(const P& pol, const Geom& g, int x0
       }
     } else {
 #pragma unroll
-      for (int oz = 0; oz < kT3; ++oz) {
+      for (int oz = 0; oz < TZ; ++oz) {
         A a[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) a[c] = A();
@@ -342,28 +349,43 @@ __device__ __forceinline__ void stencil_cube(const P& pol, const Geom& g, int x0
     }
   }
   __syncthreads();
-  // y
-  for (int it = threadIdx.x; it < kT3 * kT3 * L; it += NT) {
-    const int oz = it / (kT3 * L), rem = it - oz * (kT3 * L);
-    const int oy = rem / L, xx = rem - oy * L;
-    A a[NC];
+  // y, into registers first
+  constexpr int NY = TZ * kT3 * L, KY = (NY + NT - 1) / NT;
+  A ay[KY][NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) a[c] = A();
+  for (int j = 0; j < KY; ++j) {
+    const int it = threadIdx.x + j * NT;
+    if (NY % NT == 0 || it < NY) {
+      const int oz = it / (kT3 * L), rem = it - oz * (kT3 * L);
+      const int oy = rem / L, xx = rem - oy * L;
 #pragma unroll
-    for (int k = 0; k < W; ++k)
+      for (int c = 0; c < NC; ++c) ay[j][c] = A();
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        if constexpr (P::kBox)
-          a[c] += sm.z[c][oz][oy + k][xx];
-        else
-          a[c] = fma(A(pol.wt(k)), sm.z[c][oz][oy + k][xx], a[c]);
-      }
+      for (int k = 0; k < W; ++k)
 #pragma unroll
-    for (int c = 0; c < NC; ++c) sm.y[c][oz][oy][xx] = a[c];
+        for (int c = 0; c < NC; ++c) {
+          if constexpr (P::kBox)
+            ay[j][c] += sm.z[c][oz][oy + k][xx];
+          else
+            ay[j][c] = fma(A(pol.wt(k)), sm.z[c][oz][oy + k][xx], ay[j][c]);
+        }
+    }
+  }
+  __syncthreads();
+  auto& sy = sm.y();
+#pragma unroll
+  for (int j = 0; j < KY; ++j) {
+    const int it = threadIdx.x + j * NT;
+    if (NY % NT == 0 || it < NY) {
+      const int oz = it / (kT3 * L), rem = it - oz * (kT3 * L);
+      const int oy = rem / L, xx = rem - oy * L;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sy[c][oz][oy][xx] = ay[j][c];
+    }
   }
   __syncthreads();
   // x, and the outputs
-  for (int it = threadIdx.x; it < kT3 * kT3 * kT3; it += NT) {
+  for (int it = threadIdx.x; it < TZ * kT3 * kT3; it += NT) {
     const int oz = it / (kT3 * kT3), oy = (it / kT3) % kT3, ox = it % kT3;
     A a[NC];
 #pragma unroll
@@ -373,9 +395,9 @@ __device__ __forceinline__ void stencil_cube(const P& pol, const Geom& g, int x0
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         if constexpr (P::kBox)
-          a[c] += sm.y[c][oz][oy][ox + k];
+          a[c] += sy[c][oz][oy][ox + k];
         else
-          a[c] = fma(A(pol.wt(k)), sm.y[c][oz][oy][ox + k], a[c]);
+          a[c] = fma(A(pol.wt(k)), sy[c][oz][oy][ox + k], a[c]);
       }
     const int gx = x0 + ox, gy = y0 + oy, gz = z0 + oz;
     if (gx < g.nx && gy < g.ny && gz < g.nz)

@@ -109,7 +109,8 @@ def test_warp_integer_shift_is_exact(L):
 
 # ------------------------------------------------------------------ loss and gradients
 # the two tilings of the stencil passes: 32 x 8 columns marching through z
-# chunks, and 8^3 cubes (the default below 2^20 voxels)
+# chunks, and bricks of 8 x 8 columns, 4 or 8 planes deep (the default below
+# 2^20 voxels)
 STENCILS = [1, 2]
 
 
@@ -159,6 +160,30 @@ def test_compensated_fp32_sums_match_oracle(L, orc, window, sigma, stencil):
     e = report("g_raw(f32c)", host(gr), rg)
     assert e < 2e-5 * gmax, e
     e = report("g_smooth(f32c)", host(gs), orc.gauss(rg, sigma))
+    assert e < 2e-5 * gmax, e
+
+
+@pytest.mark.parametrize("accum", [0, 1])
+def test_deep_bricks_match_oracle(L, orc, accum):
+    """The cube form with 8-plane bricks (a volume giving at least 512 of
+    them; the smaller ragged volume above runs 4-plane bricks), ragged
+    against the brick in every axis."""
+    shape = (44, 77, 83)
+    F, M = smooth_pair(shape, 77)
+    rng = np.random.default_rng(13)
+    u = (rng.uniform(-2, 2, (3,) + shape)).astype(np.float32)
+    ctx = L.Context(shape, window=7, grad_sigma=1.0, accum=accum, stencil=2)
+    loss, gr, gs, cc = ctx.loss_grad(dev(F), dev(M), dev(u), cc=True)
+    rL, rg = orc.loss_grad(F, M, u, 7, 1e-5)
+    _, rcc = orc.lncc(F, orc.warp(M, u), 7, 1e-5, with_map=True)
+    print(f"[loss deep bricks accum={accum}] gpu={loss:.12f} oracle={rL:.12f}", flush=True)
+    assert abs(loss - rL) < 2e-7
+    e = report("cc(deep)", host(cc), rcc)
+    assert e < 2e-6, e
+    gmax = np.abs(rg).max()
+    e = report("g_raw(deep)", host(gr), rg)
+    assert e < 2e-5 * gmax, e
+    e = report("g_smooth(deep)", host(gs), orc.gauss(rg, 1.0))
     assert e < 2e-5 * gmax, e
 
 

@@ -1,9 +1,10 @@
 """The two tilings of the stencil passes give the same attempts.
 
-Marching 32 x 8 columns and 8^3 cubes sum the same box and Gaussian terms in
+Marching 32 x 8 columns and bricks of 8 x 8 columns (4 planes deep below
+512 bricks of 8 planes, else 8) sum the same box and Gaussian terms in
 different orders (FP64 or compensated FP32 sums), so the candidate fields of a
 run differ only by rounding and the accept/reject decisions coincide.  Shapes
-are ragged against both tilings (and against the cube edge 8); the oracle
+are ragged against both tilings (and against the brick edges); the oracle
 parity of each form is in test_gpu_parity.py."""
 import numpy as np
 import pytest
@@ -29,7 +30,8 @@ def host(t):
 @pytest.mark.parametrize("accum", [0, 1])
 @pytest.mark.parametrize("shape,window,sigma", [((13, 9, 30), 3, 0.6),
                                                 ((20, 37, 70), 7, 1.0),
-                                                ((40, 48, 56), 9, 1.3)])
+                                                ((40, 48, 56), 9, 1.3),
+                                                ((44, 77, 83), 7, 1.0)])
 def test_cube_and_march_runs_agree(L, shape, window, sigma, accum):
     from paper_2603_19371_amd import phantoms
     ph = phantoms.brain(shape, seed=sum(shape) + window)
