@@ -403,8 +403,10 @@ lmr_status lmr_batch_sync(lmr_batch* b);
  * (0 = normal operation, the default). */
 lmr_status lmr_batch_test_residency(lmr_batch* b, int late_block);
 lmr_ctx* lmr_batch_pair(lmr_batch* b, int i);
-/* Tiling knobs: target tile count per pair, minimum z-chunk, persistent
- * blocks per CU (0 = as many as fit). */
+/* Tiling knobs: target tile count per pair (0, the default: each pair tiled
+ * as a stand-alone context's marching passes tile it, so that a pair's run
+ * is bit for bit the per-pair run; else 64 ... 2^20), minimum z-chunk (4 ...
+ * 256; unused with target 0), persistent blocks per CU (0 = as many as fit). */
 lmr_status lmr_batch_set_config(lmr_batch* b, int target_tiles, int min_cz,
                                 int blocks_per_cu);
 lmr_status lmr_batch_get_config(lmr_batch* b, int cfg[3]);

@@ -118,7 +118,7 @@ lmr_status enqueue_attempt(lmr_ctx* c, const void* F, const void* M, int force) 
   LMR_HIP(mark(LMR_K_FWD, 0));
   if (sim == LMR_SIM_LNCC)
     LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, c->st, c->maps, c->partials,
-                       nullptr, s));
+                       c->nparts, nullptr, s));
   else if (sim == LMR_SIM_MI)
     LMR_HIP(launch_mi_fwd(F, c->img, c->Mw, c->g, c->p.mi_bins, c->mi_map, c->mi_hpart,
                           c->mi_p, c->mi_tab, c->partials, c->st, s));
@@ -319,7 +319,7 @@ lmr_status lmr_begin(lmr_ctx* c, const void* F, const void* M, const float* fiel
     c->fstat_of = F;
     LMR_HIP(launch_warp(M, c->img, c->U[0], c->g, c->Mw, nullptr, s));
     LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, nullptr, c->maps,
-                       c->partials, nullptr, s));
+                       c->partials, c->nparts, nullptr, s));
   } else if (sim == LMR_SIM_MI) {
     LMR_HIP(launch_mi_range(F, M, c->img, c->g, c->p.mi_bins, c->mi_rpart, c->mi_map, s));
     c->mi_of[0] = F;
@@ -484,7 +484,7 @@ lmr_status lmr_loss_grad(lmr_ctx* c, const void* F, const void* M, const float* 
     c->fstat_of = F;
     LMR_HIP(launch_warp(M, c->img, u, c->g, c->Mw, nullptr, s));
     LMR_HIP(launch_fwd(F, c->img, c->Mw, c->fstat, c->g, c->p, nullptr, c->maps,
-                       c->partials, cc_map, s));
+                       c->partials, c->nparts, cc_map, s));
   } else if (c->p.similarity == LMR_SIM_MI) {
     if (cc_map) return LMR_EINVAL;
     LMR_HIP(launch_mi_range(F, M, c->img, c->g, c->p.mi_bins, c->mi_rpart, c->mi_map, s));

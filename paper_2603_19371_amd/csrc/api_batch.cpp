@@ -33,7 +33,8 @@ struct lmr_batch {
   const void* kernel = nullptr;
   int cus = 0, max_blocks_per_cu = 0;
   // tuned configuration
-  int target_tiles = 2048, min_cz = 16, blocks_per_cu = 0;
+  // target_tiles 0: each pair tiled as a stand-alone context's march tiles it
+  int target_tiles = 0, min_cz = 16, blocks_per_cu = 0;
   int n_update_items = 0, n_tiles = 0;
   unsigned long long timeout = 0;  // barrier timeout in wall-clock ticks
   unsigned long long start_timeout = 0;  // co-residency check, wall-clock ticks
@@ -57,7 +58,9 @@ lmr_status layout(lmr_batch* b) {
   const int ty = batch_tile_rows();
   for (int i = 0; i < b->npairs; ++i) {
     BatchPair& P = b->host[i];
-    P.t = make_tiling(P.g.nz, P.g.ny, P.g.nx, ty, b->target_tiles, b->min_cz);
+    P.t = b->target_tiles > 0
+              ? make_tiling(P.g.nz, P.g.ny, P.g.nx, ty, b->target_tiles, b->min_cz)
+              : march_tiling(P.g, b->p.window / 2);
     const int ucols = ((P.g.nx + kBatchUpdateTX - 1) / kBatchUpdateTX) *
                       ((P.g.ny + kBatchUpdateTY - 1) / kBatchUpdateTY);
     P.ucz = static_cast<int>(((long long)P.g.nz * ucols + kBatchUpdateItems - 1) /
@@ -297,8 +300,8 @@ lmr_status lmr_batch_get_config(lmr_batch* b, int cfg[3]) {
 
 lmr_status lmr_batch_set_config(lmr_batch* b, int target_tiles, int min_cz,
                                 int blocks_per_cu) {
-  if (!b || target_tiles < 64 || target_tiles > (1 << 20) || min_cz < 4 || min_cz > 256 ||
-      blocks_per_cu < 0)
+  if (!b || (target_tiles != 0 && (target_tiles < 64 || target_tiles > (1 << 20))) ||
+      min_cz < 4 || min_cz > 256 || blocks_per_cu < 0)
     return LMR_EINVAL;
   b->target_tiles = target_tiles;
   b->min_cz = min_cz;
@@ -331,11 +334,13 @@ lmr_status lmr_batch_tune(lmr_batch* b, const void* const* fixed, const void* co
   LMR_HIP(hipEventCreate(&e1));
   double best = 1e30;
   int bt = b->target_tiles, bm = b->min_cz, bb = b->blocks_per_cu;
-  const int tts[] = {1024, 2048, 4096, 8192};
+  // target 0 (the per-pair tiling) does not use the chunk minimum
+  const int tts[] = {0, 1024, 2048, 4096, 8192};
   const int mcs[] = {8, 16, 32};
   for (int tt : tts)
     for (int mc : mcs)
       for (int bpc = 1; bpc <= b->max_blocks_per_cu; ++bpc) {
+        if (tt == 0 && mc != 16) continue;
         lmr_status st = lmr_batch_set_config(b, tt, mc, bpc);
         if (st == LMR_OK) st = lmr_batch_begin(b, fixed, moving, nullptr);
         if (st == LMR_OK) st = lmr_batch_step(b, 1, 0);  // warm-up

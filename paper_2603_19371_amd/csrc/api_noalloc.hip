@@ -93,7 +93,7 @@ extern "C" lmr_status lmr_loss_grad_noalloc(const void* F, const void* M, lmr_dt
                         p->max_retries};
   LMR_HIP(launch_fstat(F, img, g, *p, fstat, stream));
   LMR_HIP(launch_warp(M, img, u, g, Mw, nullptr, stream));
-  LMR_HIP(launch_fwd(F, img, Mw, fstat, g, *p, nullptr, maps, parts, cc_map, stream));
+  LMR_HIP(launch_fwd(F, img, Mw, fstat, g, *p, nullptr, maps, parts, nparts, cc_map, stream));
   LMR_HIP(launch_decide(dst, parts, nparts, N, dp, 2, -1, 0.0, loss_dev, stream));
   if (g_raw || g_smooth) {
     float* gr = g_raw ? g_raw : graw;

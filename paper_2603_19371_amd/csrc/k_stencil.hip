@@ -2,6 +2,8 @@
 // LNCC forward (P2), LNCC + warp backward (P4) and Gaussian smoothing (P5).
 // One block per tile; block ids are remapped so that each XCD receives a
 // contiguous range of tiles and shares their halos in its L2.
+#include <algorithm>
+
 #include "stencil.h"
 
 namespace lmr {
@@ -64,7 +66,40 @@ __global__ void __launch_bounds__(kCubeThreads)
   pol.end_tile(loc, b);
 }
 
-Tiling tiling_of(const Geom& g) { return make_tiling(g.nz, g.ny, g.nx, kTY); }
+}  // namespace
+
+// Chunk length of the march.  A launch runs its blocks in rounds of
+// 4 x CUs co-resident ones (the forward and backward passes' occupancy with
+// FP64 sums and window 7; the smoothing pass holds 8 per CU but is bound by
+// memory and runs fastest on the same chunks), and each block of a round
+// marches its chunk plus the 2R halo planes, so a launch lasts about
+// ceil(tiles / (4 CUs)) x (cz + 2R) plane steps.  Among the chunk lengths
+// not below make_tiling's floor, take the one that minimises this (the longer
+// chunk on a tie).  It does not depend on the kernel: a box sum's rounding
+// depends on where its chunk starts, and the batched form reproduces a pair's
+// run by using the same tiling for all passes.
+Tiling march_tiling(const Geom& g, int R) {
+  Tiling t = make_tiling(g.nz, g.ny, g.nx, kTY);
+  const long long cols = (long long)t.tiles_x * t.tiles_y;
+  const long long cap = 4LL * device_cus();
+  const int floor_cz = std::min(march_floor_cz(cols, g.nz), g.nz);
+  long long best = -1;
+  for (int n = 1; n <= g.nz; ++n) {
+    const int cz = (g.nz + n - 1) / n;
+    if (cz < floor_cz) break;
+    const int chunks = (g.nz + cz - 1) / cz;
+    if (chunks != n) continue;  // the same chunk length as a smaller n
+    const long long cost = ((cols * chunks + cap - 1) / cap) * (cz + 2 * R);
+    if (best < 0 || cost < best) {
+      best = cost;
+      t.cz = cz;
+      t.nchunks = chunks;
+    }
+  }
+  return t;
+}
+
+namespace {
 
 // The forward policy's block reduction is sized for its block: one policy
 // type serves both forms, so both forms launch blocks of the same size.
@@ -108,7 +143,7 @@ hipError_t run(const P& pol, const Geom& g, bool cubes, const DevState* st, int 
                          pol, g, cx, cy, st, need);
     return hipGetLastError();
   }
-  const Tiling t = tiling_of(g);
+  const Tiling t = march_tiling(g, R);
   hipLaunchKernelGGL((k_stencil<R, kTY, P>), dim3(t.tiles()), dim3(kTX * kTY), 0, s, pol,
                      g, t, st, need);
   return hipGetLastError();
@@ -140,7 +175,8 @@ hipError_t fstat_t(const T* F, const Geom& g, const lmr_params& p, double* fstat
 template <typename T, typename Acc>
 hipError_t fwd_t(const T* F, const float* Mw, const double* fstat, const Geom& g,
                  const lmr_params& p, const DevState* st, float* maps, double* partials,
-                 float* cc, hipStream_t s) {
+                 int nparts, float* cc, hipStream_t s) {
+  if (fwd_num_blocks(g, p) != nparts) return hipErrorInvalidValue;
   FwdPol<T, kTX * kTY, Acc> pol;
   pol.F = F;
   pol.Mw = Mw;
@@ -188,7 +224,7 @@ hipError_t smooth_r(const float* in, float* out, const Geom& g, const lmr_params
 }  // namespace
 
 int fwd_num_blocks(const Geom& g, const lmr_params& p) {
-  return use_cubes(g, p) ? cube_count(g) : tiling_of(g).tiles();
+  return use_cubes(g, p) ? cube_count(g) : march_tiling(g, p.window / 2).tiles();
 }
 
 int gauss_radius(double sigma) {
@@ -212,17 +248,20 @@ hipError_t launch_fstat(const void* F, lmr_dtype t, const Geom& g, const lmr_par
 
 hipError_t launch_fwd(const void* F, lmr_dtype t, const float* Mw, const double* fstat,
                       const Geom& g, const lmr_params& p, const DevState* st, float* maps,
-                      double* partials, float* cc_map, hipStream_t s) {
+                      double* partials, int nparts, float* cc_map, hipStream_t s) {
   if (t == LMR_BF16) {
     const uint16_t* f = static_cast<const uint16_t*>(F);
     return p.accum == LMR_ACC_F32C
-               ? fwd_t<uint16_t, F32C>(f, Mw, fstat, g, p, st, maps, partials, cc_map, s)
-               : fwd_t<uint16_t, double>(f, Mw, fstat, g, p, st, maps, partials, cc_map, s);
+               ? fwd_t<uint16_t, F32C>(f, Mw, fstat, g, p, st, maps, partials, nparts, cc_map,
+                                       s)
+               : fwd_t<uint16_t, double>(f, Mw, fstat, g, p, st, maps, partials, nparts,
+                                         cc_map, s);
   }
   const float* f = static_cast<const float*>(F);
   return p.accum == LMR_ACC_F32C
-             ? fwd_t<float, F32C>(f, Mw, fstat, g, p, st, maps, partials, cc_map, s)
-             : fwd_t<float, double>(f, Mw, fstat, g, p, st, maps, partials, cc_map, s);
+             ? fwd_t<float, F32C>(f, Mw, fstat, g, p, st, maps, partials, nparts, cc_map, s)
+             : fwd_t<float, double>(f, Mw, fstat, g, p, st, maps, partials, nparts, cc_map,
+                                    s);
 }
 
 hipError_t launch_bwd(const void* F, const void* M, lmr_dtype t, const float* Mw,

@@ -13,6 +13,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
 
 namespace lmr {
 
@@ -256,22 +257,24 @@ hipError_t launch_warp(const void* M, lmr_dtype t, const float* u, const Geom& g
   return hipGetLastError();
 }
 
-namespace {
-
 // compute units of the current device, cached per device (a tiling
 // heuristic only: 256 when the query fails)
 int device_cus() {
-  static int cus[64] = {};
+  static std::atomic<int> cus[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (cus[dev] == 0) {
+  int v = cus[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
     int n = 0;
     const bool ok =
         hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess;
-    cus[dev] = ok && n > 0 ? n : 256;
+    v = ok && n > 0 ? n : 256;
+    cus[dev].store(v, std::memory_order_relaxed);
   }
-  return cus[dev];
+  return v;
 }
+
+namespace {
 
 // z-chunk of the staged form.  The blocks of a launch are co-resident and
 // each marches its chunk plane by plane, so a launch lasts about (most blocks

@@ -377,7 +377,12 @@ struct StepBuffers {
   double* probe;    // scalar loss written by the probe reduction
 };
 
+// The forward pass's block count (one cc partial per block); launch_fwd
+// checks its launch against it.
 int fwd_num_blocks(const Geom& g, const lmr_params& p);
+// compute units of the current device (cached per device; 256 when the query
+// fails)
+int device_cus();
 int gauss_radius(double sigma);
 
 hipError_t launch_warp(const void* M, lmr_dtype t, const float* u, const Geom& g,
@@ -439,9 +444,11 @@ hipError_t launch_fstat(const void* F, lmr_dtype t, const Geom& g, const lmr_par
                         double* fstat, hipStream_t s);
 // P2: LNCC forward; writes adjoint maps, per-block partials and optionally cc.
 // fstat: launch_fstat's output for the same F.
+// nparts: fwd_num_blocks(g, p), the partials' length (hipErrorInvalidValue if
+// the launch would differ, e.g. on a device with another CU count).
 hipError_t launch_fwd(const void* F, lmr_dtype t, const float* Mw, const double* fstat,
                       const Geom& g, const lmr_params& p, const DevState* st, float* maps,
-                      double* partials, float* cc_map, hipStream_t s);
+                      double* partials, int nparts, float* cc_map, hipStream_t s);
 // P3: FP64 reduction of the partials and the decision.
 // mode 0: attempt (force -1/0/1), mode 1: begin (lambda0), mode 2: probe.
 hipError_t launch_decide(DevState* st, const double* partials, int nparts,

@@ -83,6 +83,16 @@ struct Tiling {
 
 constexpr int kMinTiles = 256;  // one tile per CU
 
+// Floor on the chunk length: 8 planes while that still gives every CU a tile
+// (the 2R halo planes stay a moderate share), else 4, else 2 when 4 would
+// leave CUs without a tile (small pyramid levels: the march of a chunk is
+// their latency).
+__host__ __device__ inline int march_floor_cz(long long cols, int nz) {
+  return cols * ((nz + 7) / 8) >= kMinTiles   ? 8
+         : cols * ((nz + 3) / 4) >= kMinTiles ? 4
+                                              : 2;
+}
+
 // z-chunk: long enough that the 2R halo planes of a chunk stay a small
 // fraction when the volume is large, short enough that small volumes still
 // give a few hundred tiles.  target_tiles and min_cz are tuning knobs.
@@ -96,19 +106,18 @@ __host__ __device__ inline Tiling make_tiling(int nz, int ny, int nx, int ty,
   const int want = (target_tiles + cols - 1) / cols;
   int cz = (nz + want - 1) / want;
   if (cols * ((nz + min_cz - 1) / min_cz) >= target_tiles / 2 && cz < min_cz) cz = min_cz;
-  // floor on the chunk length: 8 planes while that still gives every CU a
-  // tile (the 2R halo planes stay a moderate share), else 4, else 2 when 4
-  // would leave CUs without a tile (small pyramid levels: the march of a
-  // chunk is their latency)
-  const int floor_cz = cols * ((nz + 7) / 8) >= kMinTiles   ? 8
-                       : cols * ((nz + 3) / 4) >= kMinTiles ? 4
-                                                            : 2;
+  const int floor_cz = march_floor_cz(cols, nz);
   if (cz < floor_cz) cz = floor_cz;
   if (cz > nz) cz = nz;
   t.cz = cz;
   t.nchunks = (nz + cz - 1) / cz;
   return t;
 }
+
+// The march's tiling of a volume for stencil radius R on the current device
+// (k_stencil.hip): every pass of a per-pair attempt, and by default each pair
+// of the batched form.
+Tiling march_tiling(const Geom& g, int R);
 
 // LDS of one stencil tile: the staged raw inputs and the y-pass sums.
 template <int R, int TY, class P>
