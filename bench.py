@@ -560,6 +560,26 @@ def run_batch(a):
                 "algorithmic_bytes_per_launch": attempt_bytes(4) * ntot,
                 "mean_launch_ms": round(per_attempt_s * 1e3, 5),
                 "launches_timed": a.steps * BATCH_ITERS}
+    # the same pairs as stand-alone contexts, one after another: a one-level
+    # pyramid per pair replays its attempts as one HIP graph
+    kw = dict(window=WINDOW, grad_sigma=SIGMA, accum=ACCUM[a.accum])
+    pyrs = [_lib.Pyramid(sh, (1,), **kw) for sh in BATCH_SHAPES]
+    outs = [torch.empty((3,) + tuple(sh), device="cuda") for sh in BATCH_SHAPES]
+
+    def per_pair_once():
+        for i, pyr in enumerate(pyrs):
+            pyr.run(Fs[i], Ms[i], [BATCH_ITERS], lambda0=1.0, out=outs[i])
+    progress("16 pairs as stand-alone graph replays")
+    per_pair_once()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(a.steps):
+        per_pair_once()
+    torch.cuda.synchronize()
+    seq_s = (time.perf_counter() - t2) / a.steps
+    seq_att = sum(int(np.prod(sh)) * int(p.level(0).state()["attempts"])
+                  for sh, p in zip(BATCH_SHAPES, pyrs))
+    del pyrs, outs
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(Fs[0].cpu().numpy(), Ms[0].cpu().numpy(),
@@ -570,6 +590,10 @@ def run_batch(a):
                           "graph, autotuned tiling",
               "pairs": len(BATCH_SHAPES), "voxel_attempts_per_step": vox_att}
     detail = {"tuned_config": cfg, "tune_ms_per_attempt": tune_ms,
+              "per_pair_sequential": {"value": round(seq_att / seq_s, 1),
+                                      "ms_per_run": round(seq_s * 1e3, 3),
+                                      "attempt_ms": round(seq_s / BATCH_ITERS * 1e3, 4)},
+              "batched_speedup_vs_sequential": round(value / (seq_att / seq_s), 3),
               "accepted_losses": [b.pair(i).state()["loss"] for i in range(len(BATCH_SHAPES))],
               "kernel_source_sha": source_sha()}
     return "f32", value, elapsed, config, roofline, cpu, detail

@@ -44,6 +44,12 @@ __device__ __forceinline__ uint16_t f2bf(float v) {
 __device__ __forceinline__ float bf2f(uint16_t h) {
   return __uint_as_float(static_cast<uint32_t>(h) << 16);
 }
+// Eight BF16 operand slots from two groups of four (bit patterns).
+__device__ __forceinline__ b8 cat_bf16(s4 lo, s4 hi) {
+  typedef short s8 __attribute__((ext_vector_type(8)));
+  const s8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_bit_cast(b8, v);
+}
 
 // K = 16 per instruction: 4 BF16 per lane.
 struct K16 {
@@ -246,9 +252,29 @@ __global__ void __launch_bounds__(256) k_conv_tile(ConvArgs a) {
     for (int dz = 0; dz < 3; ++dz) {
       const uint16_t* xp = s_x + xr_base + dz * kCH * kCH * kPitch;
       const uint16_t* wp = s_w + wr_base + dz * 9 * 16 * NT * kPitch;
+      // taps 2p and 2p + 1 as one K = 32 product (each lane's eight K slots:
+      // its four channels of the first tap, then the same four of the
+      // second, in both operands); the ninth tap as a K = 16 product
 #pragma unroll
-      for (int t9 = 0; t9 < 9; ++t9) {
-        const int dy = t9 / 3, dx = t9 % 3;  // halo coordinates
+      for (int tp = 0; tp < 4; ++tp) {
+        const int ta = 2 * tp, tb = ta + 1;
+        b8 w[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+          w[n] = cat_bf16(*reinterpret_cast<const s4*>(wp + (ta * NT + n) * 16 * kPitch),
+                          *reinterpret_cast<const s4*>(wp + (tb * NT + n) * 16 * kPitch));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const b8 xv = cat_bf16(
+              *reinterpret_cast<const s4*>(xp + ((r + ta / 3) * kCH + ta % 3) * kPitch),
+              *reinterpret_cast<const s4*>(xp + ((r + tb / 3) * kCH + tb % 3) * kPitch));
+#pragma unroll
+          for (int n = 0; n < NT; ++n)
+            acc[n][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[n], xv, acc[n][r], 0, 0, 0);
+        }
+      }
+      {
+        constexpr int t9 = 8, dy = 2, dx = 2;  // halo coordinates of the ninth tap
         s4 w[NT];
 #pragma unroll
         for (int n = 0; n < NT; ++n)
