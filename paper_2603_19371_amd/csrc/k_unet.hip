@@ -480,31 +480,43 @@ __global__ void __launch_bounds__(256, 2) k_wgrad(WgradArgs a) {
     const uint16_t* xs[3];
 #pragma unroll
     for (int dz = 0; dz < 3; ++dz) xs[dz] = s_xt + ((z + 2 + dz) % 3) * kWgSlot;
+    // rows 2p and 2p + 1 as one K = 32 product: each lane's eight K slots
+    // are its four voxels of the first row, then the same four of the second
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int yl = 4 * wv + r;
-      const s4 bv = *reinterpret_cast<const s4*>(&s_dt[(yl * 16 + m) * kWgPD + 4 * kq]);
+    for (int rp = 0; rp < 2; ++rp) {
+      const int yl = 4 * wv + 2 * rp;
+      const s4 bv0 = *reinterpret_cast<const s4*>(&s_dt[(yl * 16 + m) * kWgPD + 4 * kq]);
+      const s4 bv1 = *reinterpret_cast<const s4*>(&s_dt[((yl + 1) * 16 + m) * kWgPD + 4 * kq]);
       if (ib == 0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bs += bf2f(static_cast<uint16_t>(bv[i]));
+        for (int i = 0; i < 4; ++i) bs += bf2f(static_cast<uint16_t>(bv0[i]));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bs += bf2f(static_cast<uint16_t>(bv1[i]));
       }
+      const b8 bv = cat_bf16(bv0, bv1);
 #pragma unroll
       for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
-          // halo voxels 4 kq .. 4 kq + 5 of row yl + dy, channel m
-          const uint16_t* p = xs[dz] + ((yl + dy) * 16 + m) * kWgPX + 4 * kq;
-          const uint2 w01 = *reinterpret_cast<const uint2*>(p);
-          const unsigned w2 = *reinterpret_cast<const unsigned*>(p + 4);
-          const unsigned a0 = __builtin_amdgcn_alignbit(w01.y, w01.x, 16);
-          const unsigned a1 = __builtin_amdgcn_alignbit(w2, w01.y, 16);
-          const s4 opm = __builtin_bit_cast(s4, uint2{w01.x, w01.y});  // dx = -1
-          const s4 op0 = __builtin_bit_cast(s4, uint2{a0, a1});        // dx = 0
-          const s4 opp = __builtin_bit_cast(s4, uint2{w01.y, w2});     // dx = +1
+          // halo voxels 4 kq .. 4 kq + 5 of rows yl + dy and yl + 1 + dy,
+          // channel m; the three x taps are one-voxel shifts of them
+          s4 op[2][3];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const uint16_t* p = xs[dz] + ((yl + h + dy) * 16 + m) * kWgPX + 4 * kq;
+            const uint2 w01 = *reinterpret_cast<const uint2*>(p);
+            const unsigned w2 = *reinterpret_cast<const unsigned*>(p + 4);
+            const unsigned a0 = __builtin_amdgcn_alignbit(w01.y, w01.x, 16);
+            const unsigned a1 = __builtin_amdgcn_alignbit(w2, w01.y, 16);
+            op[h][0] = __builtin_bit_cast(s4, uint2{w01.x, w01.y});  // dx = -1
+            op[h][1] = __builtin_bit_cast(s4, uint2{a0, a1});        // dx = 0
+            op[h][2] = __builtin_bit_cast(s4, uint2{w01.y, w2});     // dx = +1
+          }
           const int t = dz * 9 + dy * 3;
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(opm, bv, acc[t], 0, 0, 0);
-          acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(op0, bv, acc[t + 1], 0, 0, 0);
-          acc[t + 2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(opp, bv, acc[t + 2], 0, 0, 0);
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            acc[t + d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cat_bf16(op[0][d], op[1][d]),
+                                                                 bv, acc[t + d], 0, 0, 0);
         }
     }
   }
