@@ -406,7 +406,11 @@ lmr_ctx* lmr_batch_pair(lmr_batch* b, int i);
 /* Tiling knobs: target tile count per pair (0, the default: each pair tiled
  * as a stand-alone context's marching passes tile it, so that a pair's run
  * is bit for bit the per-pair run; else 64 ... 2^20), minimum z-chunk (4 ...
- * 256; unused with target 0), persistent blocks per CU (0 = as many as fit). */
+ * 256; unused with target 0), persistent blocks per CU (0 = as many as fit;
+ * -1 = no persistent kernel: each phase of an attempt is one launch over the
+ * work items of all pairs, the same items and results, 5 to 8 launches per
+ * attempt).  Pairs that a stand-alone context runs on 4-plane bricks run on
+ * the same bricks here (either mode); the others march. */
 lmr_status lmr_batch_set_config(lmr_batch* b, int target_tiles, int min_cz,
                                 int blocks_per_cu);
 lmr_status lmr_batch_get_config(lmr_batch* b, int cfg[3]);

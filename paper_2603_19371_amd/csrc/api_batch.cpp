@@ -32,6 +32,7 @@ struct lmr_batch {
   std::vector<double*> partials;  // per pair, sized for the smallest z-chunk
   const void* kernel = nullptr;
   int cus = 0, max_blocks_per_cu = 0;
+  bool any_march = false, any_bricks = false;  // the stencil forms of the pairs
   // tuned configuration
   // target_tiles 0: each pair tiled as a stand-alone context's march tiles it
   int target_tiles = 0, min_cz = 16, blocks_per_cu = 0;
@@ -66,10 +67,11 @@ lmr_status layout(lmr_batch* b) {
     P.ucz = static_cast<int>(((long long)P.g.nz * ucols + kBatchUpdateItems - 1) /
                              kBatchUpdateItems);
     P.ucz = std::min(std::max(P.ucz, kBatchUpdateMinCz), kBatchUpdateMaxCz);
+    P.ntiles = P.bricks ? brick_count(P.g, kBatchBrickTZ) : P.t.tiles();
     P.utile0 = vox;
     P.tile0 = tiles;
     vox += ucols * ((P.g.nz + P.ucz - 1) / P.ucz);
-    tiles += P.t.tiles();
+    tiles += P.ntiles;
   }
   b->n_update_items = vox;
   b->n_tiles = tiles;
@@ -89,6 +91,14 @@ int grid_of(const lmr_batch* b) {
 }
 
 lmr_status enqueue_steps(lmr_batch* b, int n) {
+  if (b->blocks_per_cu < 0) {  // one launch per phase
+    const int rb = b->p.window / 2, rg = gauss_r(b->p.grad_sigma);
+    for (int i = 0; i < n; ++i)
+      LMR_HIP(launch_batch_phases(b->img, static_cast<lmr_accum>(b->p.accum), rb, rg,
+                                  b->any_march, b->any_bricks, b->dev_pairs, b->npairs,
+                                  b->n_update_items, b->n_tiles, b->dp, b->stream));
+    return LMR_OK;
+  }
   const int grid = grid_of(b);
   for (int i = 0; i < n; ++i)
     LMR_HIP(launch_batch_attempt(b->kernel, grid, b->dev_pairs, b->npairs, b->n_update_items,
@@ -99,7 +109,7 @@ lmr_status enqueue_steps(lmr_batch* b, int n) {
 
 std::string cache_key(const lmr_batch* b) {
   char buf[128];
-  snprintf(buf, sizeof buf, "gfx950|img%d|acc%d|w%d|s%.3f|", (int)b->img, b->p.accum,
+  snprintf(buf, sizeof buf, "gfx950|v2|img%d|acc%d|w%d|s%.3f|", (int)b->img, b->p.accum,
            b->p.window, b->p.grad_sigma);
   std::string k = buf;
   for (const auto& P : b->host) {
@@ -134,7 +144,19 @@ lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes, lmr_
   if (p->tile != 1 || p->optimizer != LMR_OPT_LM || p->similarity != LMR_SIM_LNCC)
     return LMR_EINVAL;
   const int rb = p->window / 2, rg = gauss_r(p->grad_sigma);
-  const void* kernel = batch_kernel(img, static_cast<lmr_accum>(p->accum), rb, rg);
+  // pair i runs its stencils on 4-plane bricks where a stand-alone context
+  // does (small pairs), else it marches; the pair's own begin uses that form
+  std::vector<char> bricks(npairs, 0);
+  bool any_bricks = false;
+  for (int i = 0; i < npairs; ++i) {
+    const int nz = shapes[3 * i], ny = shapes[3 * i + 1], nx = shapes[3 * i + 2];
+    if (nz < 1 || ny < 1 || nx < 1) return LMR_EINVAL;
+    const Geom gi{nz, ny, nx, (long long)nz * ny * nx};
+    bricks[i] = brick_depth(gi, *p) == kBatchBrickTZ;
+    any_bricks = any_bricks || bricks[i];
+  }
+  const void* kernel =
+      batch_kernel(img, static_cast<lmr_accum>(p->accum), rb, rg, any_bricks);
   if (!kernel) return LMR_EINVAL;  // Gaussian radius beyond the instantiated range
   lmr_batch* b = new (std::nothrow) lmr_batch();
   if (!b) return LMR_ENOMEM;
@@ -144,6 +166,8 @@ lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes, lmr_
   b->dp = DecideParams{p->lambda_inc, p->lambda_dec, p->lambda_min, p->lambda_max,
                        p->tau, p->max_retries};
   b->kernel = kernel;
+  b->any_bricks = any_bricks;
+  for (int i = 0; i < npairs; ++i) b->any_march = b->any_march || !bricks[i];
   auto fail = [&](lmr_status s) {
     lmr_batch_destroy(b);
     return s;
@@ -180,22 +204,26 @@ lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes, lmr_
   b->ctx.resize(npairs, nullptr);
   b->host.resize(npairs);
   b->partials.resize(npairs, nullptr);
-  // the persistent kernel's stencils march; the pairs' own begin does too
-  lmr_params pc = *p;
-  pc.stencil = LMR_STENCIL_MARCH;
   for (int i = 0; i < npairs; ++i) {
     const int nz = shapes[3 * i], ny = shapes[3 * i + 1], nx = shapes[3 * i + 2];
+    const Geom gi{nz, ny, nx, (long long)nz * ny * nx};
+    lmr_params pc = *p;
+    pc.stencil = bricks[i] ? LMR_STENCIL_CUBE : LMR_STENCIL_MARCH;
     lmr_status st = lmr_create(&b->ctx[i], nz, ny, nx, img, &pc, b->stream);
     if (st != LMR_OK) return fail(st);
     lmr_ctx* c = b->ctx[i];
-    // partial slots for the largest tile count any tuning can produce (cz >= 2)
+    // partial slots for the largest tile count any tuning can produce (cz >=
+    // 2), or the pair's bricks
     const int ty = batch_tile_rows();
-    const size_t maxt = (size_t)((nx + kTX - 1) / kTX) * ((ny + ty - 1) / ty) * ((nz + 1) / 2);
+    const size_t maxt =
+        bricks[i] ? (size_t)brick_count(gi, kBatchBrickTZ)
+               : (size_t)((nx + kTX - 1) / kTX) * ((ny + ty - 1) / ty) * ((nz + 1) / 2);
     if (hipMalloc(&b->partials[i], sizeof(double) * maxt) != hipSuccess)
       return fail(LMR_ENOMEM);
     BatchPair& P = b->host[i];
     memset(&P, 0, sizeof P);
     P.g = c->g;
+    P.bricks = bricks[i] ? 1 : 0;
     P.U0 = c->U[0];
     P.U1 = c->U[1];
     P.G = c->G;
@@ -294,14 +322,14 @@ lmr_status lmr_batch_get_config(lmr_batch* b, int cfg[3]) {
   if (!b || !cfg) return LMR_EINVAL;
   cfg[0] = b->target_tiles;
   cfg[1] = b->min_cz;
-  cfg[2] = b->blocks_per_cu > 0 ? b->blocks_per_cu : b->max_blocks_per_cu;
+  cfg[2] = b->blocks_per_cu != 0 ? b->blocks_per_cu : b->max_blocks_per_cu;
   return LMR_OK;
 }
 
 lmr_status lmr_batch_set_config(lmr_batch* b, int target_tiles, int min_cz,
                                 int blocks_per_cu) {
   if (!b || (target_tiles != 0 && (target_tiles < 64 || target_tiles > (1 << 20))) ||
-      min_cz < 4 || min_cz > 256 || blocks_per_cu < 0)
+      min_cz < 4 || min_cz > 256 || blocks_per_cu < -1)
     return LMR_EINVAL;
   b->target_tiles = target_tiles;
   b->min_cz = min_cz;
@@ -339,8 +367,8 @@ lmr_status lmr_batch_tune(lmr_batch* b, const void* const* fixed, const void* co
   const int mcs[] = {8, 16, 32};
   for (int tt : tts)
     for (int mc : mcs)
-      for (int bpc = 1; bpc <= b->max_blocks_per_cu; ++bpc) {
-        if (tt == 0 && mc != 16) continue;
+      for (int bpc = -1; bpc <= b->max_blocks_per_cu; ++bpc) {
+        if (bpc == 0 || (tt == 0 && mc != 16)) continue;
         lmr_status st = lmr_batch_set_config(b, tt, mc, bpc);
         if (st == LMR_OK) st = lmr_batch_begin(b, fixed, moving, nullptr);
         if (st == LMR_OK) st = lmr_batch_step(b, 1, 0);  // warm-up

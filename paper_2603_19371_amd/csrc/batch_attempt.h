@@ -4,7 +4,9 @@
 // each phase and meet at a grid barrier between phases:
 //
 //   P1 update     work items: staged-update tiles (32x8 columns over a z-chunk)
-//   P2 lncc_fwd   work items: stencil tiles of a pair (partial of cc per tile)
+//   P2 lncc_fwd   work items: stencil tiles of a pair (partial of cc per tile):
+//                 marching tiles, or 4-plane bricks for the pairs a stand-alone
+//                 context runs on them
 //   P3 decide     work items: pairs (one block reduces a pair's partials)
 //   P4 lncc_bwd   stencil tiles of the pairs whose candidate was accepted
 //   P5 smooth     stencil tiles of the pairs whose candidate was accepted
@@ -15,6 +17,8 @@
 // (later launches return at once), so a residency mistake cannot hang the
 // device.
 #pragma once
+
+#include <type_traits>
 
 #include "decide.h"
 #include "lmr_batch.h"
@@ -134,6 +138,16 @@ __device__ __forceinline__ int fresh(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// origin of brick `b` of a pair (x fastest, then y, then z), as a stand-alone
+// context numbers its bricks
+__device__ __forceinline__ void brick_origin(const Geom& g, int b, int& x0, int& y0,
+                                             int& z0) {
+  const int cx = (g.nx + kT3 - 1) / kT3, cy = (g.ny + kT3 - 1) / kT3;
+  x0 = (b % cx) * kT3;
+  y0 = ((b / cx) % cy) * kT3;
+  z0 = (b / (cx * cy)) * kBatchBrickTZ;
+}
+
 // pair owning work item `it` of a list whose per-pair offsets are first[p]
 __device__ __forceinline__ int owner(const BatchPair* __restrict__ pairs, int npairs,
                                      int it, bool tiles) {
@@ -143,12 +157,134 @@ __device__ __forceinline__ int owner(const BatchPair* __restrict__ pairs, int np
   return p;
 }
 
-template <int RB, int RG, typename T, typename Acc>
+// LDS of a brick phase, in the kernels that run bricks (BR = 1) only: the
+// brick path needs more registers, so pairs that all march keep a kernel
+// without it.
+template <int R, class P, int BR>
+using BrickLds = std::conditional_t<BR != 0, CubeLds<R, P, kBatchBrickTZ>, char>;
+
+// One work item of each phase, shared by the persistent kernel (a grid-stride
+// loop per phase, grid barriers between them) and the per-phase kernels (one
+// item per block, k_batch_phases.hip).  FORM: 0 marching pairs only, 1
+// brick pairs only, 2 either; an item of a pair of the other form is skipped.
+
+// P1: closed form, compositive integration, candidate warp (and its
+// derivative, which P4 reads), one staged tile per work item
+template <typename T>
+__device__ __forceinline__ void update_item(const BatchPair* __restrict__ pairs, int npairs,
+                                            int it, StagedLds& lds) {
+  const BatchPair& P = pairs[owner(pairs, npairs, it, false)];
+  if (P.st->stalled) return;
+  UpdateArgs a = update_args_from_state(P.st, P.U0, P.U1, P.G, P.Mw, P.eps, P.compositive);
+  a.dMw = P.graw;
+  const int local = it - P.utile0;
+  const int tx = (P.g.nx + kSX - 1) / kSX, ty = (P.g.ny + kSY - 1) / kSY;
+  const int bx = (local % tx) * kSX, by = ((local / tx) % ty) * kSY;
+  const int z0 = (local / (tx * ty)) * P.ucz;
+  const int z1 = min(z0 + P.ucz, P.g.nz);
+  if (P.compositive) {
+    staged_update_tile(static_cast<const T*>(P.M), P.g, a, point_step(a, P.g), bx, by, z0, z1,
+                       lds);
+  } else {
+    const int x = bx + static_cast<int>(threadIdx.x) % kSX;
+    const int y = by + static_cast<int>(threadIdx.x) / kSX;
+    if (x < P.g.nx && y < P.g.ny)
+      for (int z = z0; z < z1; ++z) update_voxel(static_cast<const T*>(P.M), P.g, a, x, y, z);
+  }
+}
+
+// the stencil of one work item of pair P with policy pol: a brick or a
+// marching tile (LM, LB: the LDS of either form; char where not compiled)
+template <int R, int FORM, class Pol, class LM, class LB>
+__device__ __forceinline__ void stencil_item(const Pol& pol, const BatchPair& P, int local,
+                                             typename Pol::Local& loc, LM& lm, LB& lb) {
+  int x0, y0, z0;
+  if (FORM != 0 && P.bricks) {
+    if constexpr (FORM != 0) {
+      brick_origin(P.g, local, x0, y0, z0);
+      __syncthreads();  // the previous brick's last LDS reads are done
+      stencil_cube<R, kBatchBrickTZ>(pol, P.g, x0, y0, z0, loc, lb);
+    }
+  } else {
+    if constexpr (FORM != 1) {
+      tile_origin(P.t, local, kTY, x0, y0, z0);
+      stencil_tile<R, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc, lm);
+    }
+  }
+}
+
+template <int FORM>
+__device__ __forceinline__ bool other_form(const BatchPair& P) {
+  return (FORM == 0 && P.bricks) || (FORM == 1 && !P.bricks);
+}
+
+// P2: LNCC forward, one partial of cc per tile
+template <int RB, typename T, typename Acc, int FORM, class LM, class LB>
+__device__ __forceinline__ void fwd_item(const BatchPair* __restrict__ pairs, int npairs,
+                                         int it, LM& lm, LB& lb) {
+  const BatchPair& P = pairs[owner(pairs, npairs, it, true)];
+  if (P.st->stalled || other_form<FORM>(P)) return;
+  FwdPol<T, kNT, Acc> pol;
+  pol.F = static_cast<const T*>(P.F);
+  pol.Mw = P.Mw;
+  pol.fstat = P.fstat;
+  pol.maps = P.maps;
+  pol.cc = nullptr;
+  pol.partials = P.partials;
+  pol.N = static_cast<int>(P.g.N);
+  pol.inv_n = P.inv_n;
+  pol.eps = P.cc_eps;
+  const int local = it - P.tile0;
+  auto loc = pol.begin_block(P.st);
+  stencil_item<RB, FORM>(pol, P, local, loc, lm, lb);
+  pol.end_tile(loc, local);
+}
+
+// P4: LNCC and warp backward of the accepted candidates
+template <int RB, typename T, typename Acc, int FORM, class LM, class LB>
+__device__ __forceinline__ void bwd_item(const BatchPair* __restrict__ pairs, int npairs,
+                                         int it, LM& lm, LB& lb) {
+  const BatchPair& P = pairs[owner(pairs, npairs, it, true)];
+  if (fresh(&P.st->stalled) || !fresh(&P.st->accepted) || other_form<FORM>(P)) return;
+  BwdPol<T, Acc> pol;
+  pol.F = static_cast<const T*>(P.F);
+  pol.M = static_cast<const T*>(P.M);
+  pol.Mw = P.Mw;
+  pol.maps = P.maps;
+  pol.U0 = P.U0;
+  pol.U1 = P.U1;
+  pol.u_explicit = fresh(&P.st->cur) ? P.U1 : P.U0;  // the accepted candidate
+  pol.dMw = P.graw;  // stored there by P1 for the candidate
+  pol.graw = P.graw;
+  pol.g = P.g;
+  pol.inv_n = P.inv_n;
+  auto loc = pol.begin_block(nullptr);
+  stencil_item<RB, FORM>(pol, P, it - P.tile0, loc, lm, lb);
+}
+
+// P5: Gaussian smoothing of the new gradient
+template <int RG, int FORM, class LM, class LB>
+__device__ __forceinline__ void smooth_item(const BatchPair* __restrict__ pairs, int npairs,
+                                            int it, LM& lm, LB& lb) {
+  const BatchPair& P = pairs[owner(pairs, npairs, it, true)];
+  if (fresh(&P.st->stalled) || !fresh(&P.st->accepted) || other_form<FORM>(P)) return;
+  SmoothPol<RG> pol;
+  pol.in = P.graw;
+  pol.out = P.G;
+  pol.N = static_cast<int>(P.g.N);
+#pragma unroll
+  for (int k = 0; k <= 2 * RG; ++k) pol.w[k] = P.gw[k];
+  auto loc = pol.begin_block(P.st);
+  stencil_item<RG, FORM>(pol, P, it - P.tile0, loc, lm, lb);
+}
+
+template <int RB, int RG, typename T, typename Acc, int BR>
 __global__ void __launch_bounds__(kNT)
     k_batch_attempt(const BatchPair* __restrict__ pairs, int npairs, int n_update_items,
                     int n_tiles, BatchCtl* ctl, DecideParams dp,
                     unsigned long long timeout, unsigned long long start_timeout,
                     int missing) {
+  constexpr int FORM = BR ? 2 : 0;
   const int nb = gridDim.x;
   // the phases are separated by grid barriers, so their LDS is overlaid
   __shared__ union {
@@ -156,6 +292,9 @@ __global__ void __launch_bounds__(kNT)
     StencilLds<RB, kTY, FwdPol<T, kNT, Acc>> fwd;
     StencilLds<RB, kTY, BwdPol<T, Acc>> bwd;
     StencilLds<RG, kTY, SmoothPol<RG>> smo;
+    BrickLds<RB, FwdPol<T, kNT, Acc>, BR> fwd_b;
+    BrickLds<RB, BwdPol<T, Acc>, BR> bwd_b;
+    BrickLds<RG, SmoothPol<RG>, BR> smo_b;
   } lds;
   // after a barrier failure every later launch returns at once
   if (__hip_atomic_load(&ctl->error.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
@@ -164,117 +303,42 @@ __global__ void __launch_bounds__(kNT)
   unsigned long long ticket = 0;
   if (threadIdx.x == 0) ticket = count_in(ctl, missing, start_timeout) + 1;
 
-  // P1: closed form, compositive integration, candidate warp (and its
-  // derivative, which P4 reads), one staged tile per work item
-  for (int it = blockIdx.x; it < n_update_items; it += nb) {
-    const BatchPair& P = pairs[owner(pairs, npairs, it, false)];
-    if (P.st->stalled) continue;
-    UpdateArgs a = update_args_from_state(P.st, P.U0, P.U1, P.G, P.Mw, P.eps, P.compositive);
-    a.dMw = P.graw;
-    const int local = it - P.utile0;
-    const int tx = (P.g.nx + kSX - 1) / kSX, ty = (P.g.ny + kSY - 1) / kSY;
-    const int bx = (local % tx) * kSX, by = ((local / tx) % ty) * kSY;
-    const int z0 = (local / (tx * ty)) * P.ucz;
-    const int z1 = min(z0 + P.ucz, P.g.nz);
-    if (P.compositive) {
-      staged_update_tile(static_cast<const T*>(P.M), P.g, a, point_step(a, P.g), bx, by, z0,
-                         z1, lds.upd);
-    } else {
-      const int x = bx + static_cast<int>(threadIdx.x) % kSX;
-      const int y = by + static_cast<int>(threadIdx.x) / kSX;
-      if (x < P.g.nx && y < P.g.ny)
-        for (int z = z0; z < z1; ++z) update_voxel(static_cast<const T*>(P.M), P.g, a, x, y, z);
-    }
-  }
+  for (int it = blockIdx.x; it < n_update_items; it += nb)
+    update_item<T>(pairs, npairs, it, lds.upd);
   // P1 wrote only candidates (the accepted fields, the smoothed gradients
   // and the states are untouched), so a launch that fails here leaves every
   // pair as the previous launch left it
   if (!grid_sync(ctl, nb, timeout, ticket, start_timeout)) return;
-
-  // P2: LNCC forward, one partial of cc per tile
-  for (int it = blockIdx.x; it < n_tiles; it += nb) {
-    const BatchPair& P = pairs[owner(pairs, npairs, it, true)];
-    if (P.st->stalled) continue;
-    FwdPol<T, kNT, Acc> pol;
-    pol.F = static_cast<const T*>(P.F);
-    pol.Mw = P.Mw;
-    pol.fstat = P.fstat;
-    pol.maps = P.maps;
-    pol.cc = nullptr;
-    pol.partials = P.partials;
-    pol.N = static_cast<int>(P.g.N);
-    pol.inv_n = P.inv_n;
-    pol.eps = P.cc_eps;
-    const int local = it - P.tile0;
-    int x0, y0, z0;
-    tile_origin(P.t, local, kTY, x0, y0, z0);
-    auto loc = pol.begin_block(P.st);
-    stencil_tile<RB, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc, lds.fwd);
-    pol.end_tile(loc, local);
-  }
+  for (int it = blockIdx.x; it < n_tiles; it += nb)
+    fwd_item<RB, T, Acc, FORM>(pairs, npairs, it, lds.fwd, lds.fwd_b);
   if (!grid_sync(ctl, nb, timeout)) return;
-
   // P3: per-pair FP64 reduction and decision
   for (int p = blockIdx.x; p < npairs; p += nb) {
     const BatchPair& P = pairs[p];
-    decide_block<kNT>(P.st, P.partials, P.t.tiles(), P.g.N, dp, 0, -1, 0.0, nullptr);
+    decide_block<kNT>(P.st, P.partials, P.ntiles, P.g.N, dp, 0, -1, 0.0, nullptr);
   }
   if (!grid_sync(ctl, nb, timeout)) return;
-
-  // P4: LNCC and warp backward of the accepted candidates
-  for (int it = blockIdx.x; it < n_tiles; it += nb) {
-    const BatchPair& P = pairs[owner(pairs, npairs, it, true)];
-    if (fresh(&P.st->stalled) || !fresh(&P.st->accepted)) continue;
-    BwdPol<T, Acc> pol;
-    pol.F = static_cast<const T*>(P.F);
-    pol.M = static_cast<const T*>(P.M);
-    pol.Mw = P.Mw;
-    pol.maps = P.maps;
-    pol.U0 = P.U0;
-    pol.U1 = P.U1;
-    pol.u_explicit = fresh(&P.st->cur) ? P.U1 : P.U0;  // the accepted candidate
-    pol.dMw = P.graw;  // stored there by P1 for the candidate
-    pol.graw = P.graw;
-    pol.g = P.g;
-    pol.inv_n = P.inv_n;
-    int x0, y0, z0;
-    tile_origin(P.t, it - P.tile0, kTY, x0, y0, z0);
-    auto loc = pol.begin_block(nullptr);
-    stencil_tile<RB, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc, lds.bwd);
-  }
+  for (int it = blockIdx.x; it < n_tiles; it += nb)
+    bwd_item<RB, T, Acc, FORM>(pairs, npairs, it, lds.bwd, lds.bwd_b);
   if (!grid_sync(ctl, nb, timeout)) return;
-
-  // P5: Gaussian smoothing of the new gradient
-  for (int it = blockIdx.x; it < n_tiles; it += nb) {
-    const BatchPair& P = pairs[owner(pairs, npairs, it, true)];
-    if (fresh(&P.st->stalled) || !fresh(&P.st->accepted)) continue;
-    SmoothPol<RG> pol;
-    pol.in = P.graw;
-    pol.out = P.G;
-    pol.N = static_cast<int>(P.g.N);
-#pragma unroll
-    for (int k = 0; k <= 2 * RG; ++k) pol.w[k] = P.gw[k];
-    int x0, y0, z0;
-    tile_origin(P.t, it - P.tile0, kTY, x0, y0, z0);
-    auto loc = pol.begin_block(P.st);
-    stencil_tile<RG, kTY>(pol, P.g, x0, y0, z0, min(z0 + P.t.cz, P.g.nz), loc, lds.smo);
-  }
+  for (int it = blockIdx.x; it < n_tiles; it += nb)
+    smooth_item<RG, FORM>(pairs, npairs, it, lds.smo, lds.smo_b);
 }
 
-template <int RB, int RG, typename T, typename Acc>
+template <int RB, int RG, typename T, typename Acc, int BR>
 const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&k_batch_attempt<RB, RG, T, Acc>);
+  return reinterpret_cast<const void*>(&k_batch_attempt<RB, RG, T, Acc, BR>);
 }
 
-template <typename T, typename Acc>
+template <typename T, typename Acc, int BR>
 const void* kernel_for(int rb, int rg) {
 #define LMR_RG(RBV)                                    \
   switch (rg) {                                        \
-    case 0: return kernel_ptr<RBV, 0, T, Acc>();       \
-    case 1: return kernel_ptr<RBV, 1, T, Acc>();       \
-    case 2: return kernel_ptr<RBV, 2, T, Acc>();       \
-    case 3: return kernel_ptr<RBV, 3, T, Acc>();       \
-    case 4: return kernel_ptr<RBV, 4, T, Acc>();       \
+    case 0: return kernel_ptr<RBV, 0, T, Acc, BR>();   \
+    case 1: return kernel_ptr<RBV, 1, T, Acc, BR>();   \
+    case 2: return kernel_ptr<RBV, 2, T, Acc, BR>();   \
+    case 3: return kernel_ptr<RBV, 3, T, Acc, BR>();   \
+    case 4: return kernel_ptr<RBV, 4, T, Acc, BR>();   \
     default: return nullptr;                           \
   }
   switch (rb) {
@@ -287,10 +351,10 @@ const void* kernel_for(int rb, int rg) {
 #undef LMR_RG
 }
 
-template <typename Acc>
+template <typename Acc, int BR>
 const void* batch_kernel_for(lmr_dtype t, int box_radius, int gauss_radius) {
-  return t == LMR_BF16 ? kernel_for<uint16_t, Acc>(box_radius, gauss_radius)
-                       : kernel_for<float, Acc>(box_radius, gauss_radius);
+  return t == LMR_BF16 ? kernel_for<uint16_t, Acc, BR>(box_radius, gauss_radius)
+                       : kernel_for<float, Acc, BR>(box_radius, gauss_radius);
 }
 
 }  // namespace

@@ -1,5 +1,5 @@
-// Batched persistent form, FP64 box sums; the accumulator dispatch and the
-// launch of either instantiation set.
+// Batched persistent form, FP64 box sums, marching pairs only; the dispatch
+// over the instantiation sets and the launch.
 #include "batch_attempt.h"
 
 namespace lmr {
@@ -7,10 +7,14 @@ namespace lmr {
 int batch_tile_rows() { return kTY; }
 int batch_block_threads() { return kNT; }
 
-const void* batch_kernel(lmr_dtype t, lmr_accum accum, int box_radius, int gauss_radius) {
-  if (accum == LMR_ACC_F32C) return batch_kernel_f32c(t, box_radius, gauss_radius);
+const void* batch_kernel(lmr_dtype t, lmr_accum accum, int box_radius, int gauss_radius,
+                         bool bricks) {
+  if (accum == LMR_ACC_F32C)
+    return bricks ? batch_kernel_bricks_f32c(t, box_radius, gauss_radius)
+                  : batch_kernel_f32c(t, box_radius, gauss_radius);
   if (accum != LMR_ACC_F64) return nullptr;
-  return batch_kernel_for<double>(t, box_radius, gauss_radius);
+  return bricks ? batch_kernel_bricks(t, box_radius, gauss_radius)
+                : batch_kernel_for<double, 0>(t, box_radius, gauss_radius);
 }
 
 hipError_t launch_batch_attempt(const void* kernel, int grid, const BatchPair* pairs,

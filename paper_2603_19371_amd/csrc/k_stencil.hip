@@ -223,6 +223,12 @@ hipError_t smooth_r(const float* in, float* out, const Geom& g, const lmr_params
 
 }  // namespace
 
+int brick_depth(const Geom& g, const lmr_params& p) {
+  return use_cubes(g, p) ? cube_tz(g) : 0;
+}
+
+int brick_count(const Geom& g, int tz) { return cube_columns(g) * ((g.nz + tz - 1) / tz); }
+
 int fwd_num_blocks(const Geom& g, const lmr_params& p) {
   return use_cubes(g, p) ? cube_count(g) : march_tiling(g, p.window / 2).tiles();
 }

@@ -114,6 +114,12 @@ __host__ __device__ inline Tiling make_tiling(int nz, int ny, int nx, int ty,
   return t;
 }
 
+// The depth of the bricks the stencil passes of a stand-alone context run on
+// (4 or 8 planes), or 0 where they march (k_stencil.hip); and the number of
+// bricks of depth tz.
+int brick_depth(const Geom& g, const lmr_params& p);
+int brick_count(const Geom& g, int tz);
+
 // The march's tiling of a volume for stencil radius R on the current device
 // (k_stencil.hip): every pass of a per-pair attempt, and by default each pair
 // of the batched form.

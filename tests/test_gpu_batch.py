@@ -39,12 +39,13 @@ def host(t):
 @pytest.mark.parametrize("accum", [0, 1])
 def test_batch_matches_per_pair_runs(L, pairs, accum):
     """Every pair of the batch follows exactly (bitwise) the run of a
-    stand-alone context with marching stencils: same kernels, same tiling,
-    same reduction order; with either box-sum accumulator."""
+    stand-alone context: these small pairs run on 4-plane bricks in both,
+    with the same bricks and the same reduction order; with either box-sum
+    accumulator."""
     n = 6
     ref = []
     for (F, M), sh in zip(pairs, SHAPES):
-        c = L.Context(sh, window=5, accum=accum, stencil=L.LMR_STENCIL_MARCH)
+        c = L.Context(sh, window=5, accum=accum)
         c.begin(F, M)
         c.step(F, M, n)
         ref.append((host(c.field()), c.state()))
@@ -56,6 +57,57 @@ def test_batch_matches_per_pair_runs(L, pairs, accum):
         v = b.pair(i)
         assert v.state() == st_ref, (i, v.state(), st_ref)
         assert np.array_equal(host(v.field()), u_ref), i
+
+
+def test_mixed_batch_matches_per_pair_runs(L):
+    """A small pair (bricks) and a pair above 2^20 voxels (marching tiles,
+    the staged update) in one persistent launch: each follows its stand-alone
+    run bit for bit."""
+    from paper_2603_19371_amd import phantoms
+    shapes = [(24, 40, 48), (40, 64, 420)]
+    imgs = []
+    for i, sh in enumerate(shapes):
+        ph = phantoms.brain(sh, seed=60 + i)
+        imgs.append((torch.from_numpy(ph.F).cuda(), torch.from_numpy(ph.M).cuda()))
+    ref = []
+    for (F, M), sh in zip(imgs, shapes):
+        c = L.Context(sh, window=7)
+        c.begin(F, M)
+        c.step(F, M, 4)
+        ref.append((host(c.field()), c.state()))
+    b = L.Batch(shapes, window=7)
+    b.begin([F for F, _ in imgs], [M for _, M in imgs])
+    b.step(4, graph=True)
+    b.sync()
+    for i, (u_ref, st_ref) in enumerate(ref):
+        assert b.pair(i).state() == st_ref, (i, b.pair(i).state(), st_ref)
+        assert np.array_equal(host(b.pair(i).field()), u_ref), i
+
+
+@pytest.mark.parametrize("accum", [0, 1])
+def test_phase_launches_match_persistent_kernel(L, accum):
+    """One launch per phase (blocks_per_cu = -1) computes the same items as
+    the persistent kernel: identical states and fields, bit for bit, on a
+    batch of brick and marching pairs, eager and replayed."""
+    from paper_2603_19371_amd import phantoms
+    shapes = [(20, 37, 70), (40, 64, 420), (32, 32, 32)]
+    Fs, Ms = [], []
+    for i, sh in enumerate(shapes):
+        ph = phantoms.brain(sh, seed=80 + i)
+        Fs.append(torch.from_numpy(ph.F).cuda())
+        Ms.append(torch.from_numpy(ph.M).cuda())
+    ref = L.Batch(shapes, window=7, accum=accum)
+    ph_ = L.Batch(shapes, window=7, accum=accum)
+    ph_.set_config(0, 16, -1)
+    assert ph_.config()["blocks_per_cu"] == -1
+    for b in (ref, ph_):
+        b.begin(Fs, Ms)
+        b.step(2, graph=False)
+        b.step(3, graph=True)
+        b.sync()
+    for i in range(len(shapes)):
+        assert ph_.pair(i).state() == ref.pair(i).state(), i
+        assert np.array_equal(host(ph_.pair(i).field()), host(ref.pair(i).field())), i
 
 
 def test_batch_matches_staged_per_pair_run(L):
