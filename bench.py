@@ -49,9 +49,10 @@ print a line of the same form:
   abdomen  192x160x192 abdomen-like cross-modal pair (CT-like fixed, MR-like
            moving), FP32, the brain's pyramid and attempts;
   batch    16 brain-like pairs of uneven shapes (4 x 96^3, 4 x 128x160x128,
-           4 x 160x192x224, 4 x 192x160x256) advanced together, one persistent
-           launch per attempt replayed from a HIP graph, tiling autotuned,
-           150 attempts at full resolution.
+           4 x 160x192x224, 4 x 192x160x256) advanced together (the tuner
+           picks a persistent launch per attempt or one launch per phase, and
+           the tiling), replayed from a HIP graph, 150 attempts at full
+           resolution, against the same pairs as stand-alone graph replays.
   small    64 brain-like 48^3 pairs, 50 attempts each: the batched form
            against the same pairs as stand-alone contexts (graph replays),
            one after another and on four streams.
@@ -556,7 +557,8 @@ def run_batch(a):
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic_for("batch_attempt", "batch16_f32_w7"),
-                "kernel": "batch_attempt (one persistent launch per attempt)",
+                "kernel": "one batched attempt (persistent launch or one launch per "
+                          "phase, as tuned)",
                 "algorithmic_bytes_per_launch": attempt_bytes(4) * ntot,
                 "mean_launch_ms": round(per_attempt_s * 1e3, 5),
                 "launches_timed": a.steps * BATCH_ITERS}
@@ -586,8 +588,8 @@ def run_batch(a):
                            what="the smallest pair of the batch")
     config = {"workload": "16 brain-like pairs (4x96^3, 4x128x160x128, 4x160x192x224, "
                           "4x192x160x256), FP32, LNCC w=7, sigma_g=1, 150 attempts at "
-                          "full resolution, one persistent launch per attempt in a HIP "
-                          "graph, autotuned tiling",
+                          "full resolution, batched form (persistent launch or one "
+                          "launch per phase per attempt, and tiling, autotuned), HIP graph",
               "pairs": len(BATCH_SHAPES), "voxel_attempts_per_step": vox_att}
     detail = {"tuned_config": cfg, "tune_ms_per_attempt": tune_ms,
               "per_pair_sequential": {"value": round(seq_att / seq_s, 1),
@@ -607,7 +609,8 @@ SMALL_ITERS = 50
 def run_small(a):
     """Many small pairs, where one pair's kernels leave most of the GPU idle:
     64 brain-like 48^3 pairs, 50 LM attempts each at full resolution.  The
-    batched persistent form (one launch per attempt for all pairs) against
+    batched form (one persistent launch, or one launch per phase, per attempt
+    for all pairs, as tuned; the pairs on 4-plane bricks) against
     the same pairs run as stand-alone contexts (one HIP graph of 50 attempts
     per pair), one after another and spread over four streams."""
     import numpy as np
@@ -671,13 +674,15 @@ def run_small(a):
     achieved = attempt_bytes(4) * nvox * SMALL_PAIRS / per_attempt_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "batch_attempt (one persistent launch per attempt)",
+                "kernel": "one batched attempt (persistent launch or one launch per "
+                          "phase, as tuned)",
                 "algorithmic_bytes_per_launch": attempt_bytes(4) * nvox * SMALL_PAIRS,
                 "mean_launch_ms": round(per_attempt_s * 1e3, 5),
                 "launches_timed": a.steps * SMALL_ITERS}
     config = {"workload": f"{SMALL_PAIRS} brain-like pairs of 48^3, FP32, LNCC w=7, "
                           f"sigma_g=1, {SMALL_ITERS} attempts at full resolution, batched "
-                          "persistent form (one launch per attempt, HIP graph, autotuned)",
+                          "form (persistent launch or one launch per phase per attempt, "
+                          "autotuned; 4-plane bricks), HIP graph",
               "pairs": SMALL_PAIRS, "voxel_attempts_per_step": vox_att}
     detail = {"batched_ms_per_run": round(elapsed / a.steps * 1e3, 3),
               "per_pair_sequential": {"value": round(seq_v, 1), "ms_per_run": round(seq_ms, 3)},
