@@ -305,9 +305,11 @@ lmr_status lmr_decide_probe(lmr_ctx* ctx, const lmr_pair_state* in,
                             double cand_loss, int force, lmr_pair_state* out);
 
 /* ------------------------------------------------------------------------ */
-/* Kernel timing.  While a profile is open, lmr_step records a HIP event pair
- * on the context's stream around each kernel of every `stride`-th attempt
- * (at most max_attempts attempts).  lmr_profile_stop synchronises and returns
+/* Kernel timing.  While a profile is open, lmr_step records HIP events on
+ * the context's stream in every `stride`-th attempt (at most max_attempts
+ * attempts): one before its first kernel and one after each kernel, so that
+ * a kernel's duration runs from the end of the one before it (its launch gap
+ * included) to its own end.  lmr_profile_stop synchronises and returns
  * per-kernel count and duration statistics indexed by lmr_kernel. */
 typedef enum {
   LMR_K_UPDATE = 0,  /* closed form + compositive integration + candidate warp */

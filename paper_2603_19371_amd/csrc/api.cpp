@@ -94,11 +94,15 @@ lmr_status enqueue_attempt(lmr_ctx* c, const void* F, const void* M, int force) 
   hipEvent_t* ev = nullptr;
   if (pr.on) {
     if (pr.seen % pr.stride == 0 && pr.recorded < pr.max_attempts)
-      ev = &pr.ev[2 * LMR_NUM_KERNELS * pr.recorded++];
+      ev = &pr.ev[(LMR_NUM_KERNELS + 1) * pr.recorded++];
     ++pr.seen;
   }
+  // one event before the first kernel and one after each kernel: kernel k
+  // runs between events k and k + 1 (each event costs a few microseconds of
+  // stream time, so a kernel's start is the previous kernel's end)
   auto mark = [&](int k, int end) -> hipError_t {
-    return ev ? hipEventRecord(ev[2 * k + end], s) : hipSuccess;
+    if (!ev || (!end && k > 0)) return hipSuccess;
+    return hipEventRecord(ev[end ? k + 1 : 0], s);
   };
   const int sim = c->p.similarity;
   // the Adam comparator keeps every step
@@ -615,7 +619,7 @@ lmr_status lmr_profile_start(lmr_ctx* c, int max_attempts, int stride) {
   if (!c || max_attempts < 1 || stride < 1) return LMR_EINVAL;
   profile_release(c->prof);
   Profiler& pr = c->prof;
-  pr.ev.resize(2 * LMR_NUM_KERNELS * (size_t)max_attempts);
+  pr.ev.resize((LMR_NUM_KERNELS + 1) * (size_t)max_attempts);
   for (auto& e : pr.ev) {
     hipError_t err = hipEventCreate(&e);
     if (err != hipSuccess) {
@@ -645,7 +649,7 @@ lmr_status lmr_profile_stop(lmr_ctx* c, lmr_kernel_time out[LMR_NUM_KERNELS]) {
   for (int a = 0; a < pr.recorded; ++a)
     for (int k = 0; k < LMR_NUM_KERNELS; ++k) {
       float ms = 0.0f;
-      hipEvent_t* e = &pr.ev[2 * LMR_NUM_KERNELS * a + 2 * k];
+      hipEvent_t* e = &pr.ev[(LMR_NUM_KERNELS + 1) * a + k];
       if (hipEventElapsedTime(&ms, e[0], e[1]) != hipSuccess) continue;
       lmr_kernel_time& t = out[k];
       if (t.count == 0 || ms < t.min_ms) t.min_ms = ms;

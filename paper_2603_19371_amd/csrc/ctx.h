@@ -14,7 +14,7 @@ struct Profiler {
   int max_attempts = 0;
   int recorded = 0;   // attempts recorded
   long long seen = 0; // attempts enqueued while on
-  std::vector<hipEvent_t> ev;  // 2 * LMR_NUM_KERNELS per recorded attempt
+  std::vector<hipEvent_t> ev;  // LMR_NUM_KERNELS + 1 per recorded attempt
 };
 
 struct lmr_ctx {
