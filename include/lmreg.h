@@ -363,38 +363,43 @@ void lmr_pyramid_destroy(lmr_pyramid* pyr);
 /* ------------------------------------------------------------------------ */
 /* Batched form: npairs pairs of uneven shapes (shapes: host array of npairs
  * triples nz, ny, nx) advance together, each with its own lambda, loss
- * history and decision.  One step is ONE persistent launch: a grid of as many
- * blocks as fit on the GPU at once sweeps the work of all pairs phase by phase
- * (update, LNCC forward, decision, LNCC backward, smoothing) with a grid
- * barrier between phases.  The launches of lmr_batch_step are captured in a
- * HIP graph on first use and replayed.  The batch owns a non-blocking stream;
- * results of one pair are read through lmr_batch_pair (borrowed context).
- * Box side 3..9 and Gaussian radius ceil(3 sigma) <= 4 are supported (else
- * LMR_EINVAL).  Its stencils march (LMR_STENCIL_MARCH, whatever p->stencil
- * says), so a pair follows a stand-alone context with that form bit for bit.
+ * history and decision.  An attempt of all pairs runs phase by phase
+ * (update, LNCC forward, decision, LNCC backward, smoothing) over the work
+ * items of all pairs, either as one launch per phase (the default) or as ONE
+ * persistent launch per attempt: a grid of as many blocks as fit on the GPU
+ * at once sweeps the items with a grid barrier between phases
+ * (lmr_batch_set_config; both give the same results bit for bit).  The
+ * launches of lmr_batch_step are captured in a HIP graph on first use and
+ * replayed.  The batch owns a non-blocking stream; results of one pair are
+ * read through lmr_batch_pair (borrowed context).  Box side 3..9 and
+ * Gaussian radius ceil(3 sigma) <= 4 are supported (else LMR_EINVAL).  A pair
+ * that a stand-alone context with p->stencil runs on 4-plane bricks runs on
+ * the same bricks here; the others march (LMR_STENCIL_MARCH); either way a
+ * pair follows the stand-alone context with that form bit for bit.
  *
- * Co-residency.  The persistent launch needs all its blocks on the GPU at
- * once; the caller must not run other kernels at the same time on other
- * streams (another batch's steps included) that could hold the resources
- * some of its blocks need.  Each launch checks this at its first barrier:
- * when a block has waited there 2 ms while some block of the grid has not
- * even started, the launch gives up and lmr_batch_sync reports LMR_EBUSY (a
- * few milliseconds, not a timeout): the pairs keep the state of the last
- * completed launch, later launches of the same step return at once, and the
- * batch may be stepped again once the other work is done.  Any barrier wait
- * longer than 0.25 s also makes every block leave (LMR_EHIP at
- * lmr_batch_sync).  Neither can hang the device. */
+ * Co-residency (persistent launches only).  The persistent launch needs all
+ * its blocks on the GPU at once; the caller must not run other kernels at
+ * the same time on other streams (another batch's steps included) that could
+ * hold the resources some of its blocks need.  Each launch checks this at its
+ * first barrier: when a block has waited there 2 ms while some block of the
+ * grid has not even started, the launch gives up and lmr_batch_sync reports
+ * LMR_EBUSY (a few milliseconds, not a timeout): the pairs keep the state of
+ * the last completed launch, later launches of the same step return at once,
+ * and the batch may be stepped again once the other work is done.  Any
+ * barrier wait longer than 0.25 s also makes every block leave (LMR_EHIP at
+ * lmr_batch_sync).  Neither can hang the device.  One launch per phase has no
+ * such requirement. */
 typedef struct lmr_batch lmr_batch;
 lmr_status lmr_batch_create(lmr_batch** out, int npairs, const int* shapes,
                             lmr_dtype img, const lmr_params* p);
 /* Starts every pair from the identity with lambda0[i] (NULL: 1.0).  fixed[i],
  * moving[i]: device images of pair i, which must stay valid while the batch
- * steps (the persistent kernel reads them through a device table).  Returns
+ * steps (the batched kernels read them through a device table).  Returns
  * after the batch stream has finished this work. */
 lmr_status lmr_batch_begin(lmr_batch* b, const void* const* fixed,
                            const void* const* moving, const double* lambda0);
-/* Enqueues n_iters iterations (one persistent launch each); use_graph = 1
- * replays a captured HIP graph of the n_iters launches. */
+/* Enqueues n_iters iterations (one persistent launch, or one launch per
+ * phase, each); use_graph = 1 replays a captured HIP graph of them. */
 lmr_status lmr_batch_step(lmr_batch* b, int n_iters, int use_graph);
 /* Synchronises the batch stream; LMR_EBUSY if a launch was not co-resident,
  * LMR_EHIP if a barrier wait timed out (both clear, so the batch can go on). */
@@ -408,10 +413,11 @@ lmr_ctx* lmr_batch_pair(lmr_batch* b, int i);
 /* Tiling knobs: target tile count per pair (0, the default: each pair tiled
  * as a stand-alone context's marching passes tile it, so that a pair's run
  * is bit for bit the per-pair run; else 64 ... 2^20), minimum z-chunk (4 ...
- * 256; unused with target 0), persistent blocks per CU (0 = as many as fit;
- * -1 = no persistent kernel: each phase of an attempt is one launch over the
- * work items of all pairs, the same items and results, 5 to 8 launches per
- * attempt).  Pairs that a stand-alone context runs on 4-plane bricks run on
+ * 256; unused with target 0), persistent blocks per CU (-1, the default:
+ * no persistent kernel, each phase of an attempt is one launch over the work
+ * items of all pairs, the same items and results, 5 to 8 launches per
+ * attempt, and no co-residency requirement; 0 = one persistent launch per
+ * attempt with as many blocks as fit; n > 0 = n blocks per CU).  Pairs that a stand-alone context runs on 4-plane bricks run on
  * the same bricks here (either mode); the others march. */
 lmr_status lmr_batch_set_config(lmr_batch* b, int target_tiles, int min_cz,
                                 int blocks_per_cu);

@@ -34,8 +34,9 @@ struct lmr_batch {
   int cus = 0, max_blocks_per_cu = 0;
   bool any_march = false, any_bricks = false;  // the stencil forms of the pairs
   // tuned configuration
-  // target_tiles 0: each pair tiled as a stand-alone context's march tiles it
-  int target_tiles = 0, min_cz = 16, blocks_per_cu = 0;
+  // target_tiles 0: each pair tiled as a stand-alone context's march tiles it;
+  // blocks_per_cu -1: one launch per phase (no persistent kernel)
+  int target_tiles = 0, min_cz = 16, blocks_per_cu = -1;
   int n_update_items = 0, n_tiles = 0;
   unsigned long long timeout = 0;  // barrier timeout in wall-clock ticks
   unsigned long long start_timeout = 0;  // co-residency check, wall-clock ticks

@@ -97,6 +97,7 @@ def test_phase_launches_match_persistent_kernel(L, accum):
         Fs.append(torch.from_numpy(ph.F).cuda())
         Ms.append(torch.from_numpy(ph.M).cuda())
     ref = L.Batch(shapes, window=7, accum=accum)
+    ref.set_config(0, 16, 0)  # the persistent kernel
     ph_ = L.Batch(shapes, window=7, accum=accum)
     ph_.set_config(0, 16, -1)
     assert ph_.config()["blocks_per_cu"] == -1
@@ -129,10 +130,15 @@ def test_batch_matches_staged_per_pair_run(L):
     assert np.array_equal(host(b.pair(0).field()), ref)
 
 
-def test_graph_replays_match_eager_steps(L, pairs):
+@pytest.mark.parametrize("blocks_per_cu", [-1, 0])
+def test_graph_replays_match_eager_steps(L, pairs, blocks_per_cu):
+    """Replayed steps equal eager steps, in the per-phase launches (the
+    default) and in the persistent kernel."""
     Fs, Ms = [F for F, _ in pairs], [M for _, M in pairs]
     eager = L.Batch(SHAPES, window=5)
     graph = L.Batch(SHAPES, window=5)
+    eager.set_config(0, 16, blocks_per_cu)
+    graph.set_config(0, 16, blocks_per_cu)
     eager.begin(Fs, Ms)
     graph.begin(Fs, Ms)
     for rep in range(3):
@@ -157,6 +163,7 @@ def test_launch_not_co_resident_fails_fast(L, pairs):
     wait of the kernel is bounded."""
     Fs, Ms = [F for F, _ in pairs], [M for _, M in pairs]
     b = L.Batch(SHAPES, window=5)
+    b.set_config(0, 16, 0)  # the persistent kernel
     b.begin(Fs, Ms)
     b.step(2, graph=False)
     b.sync()
@@ -224,8 +231,8 @@ def config4():
 
 @pytest.mark.parametrize("tuned", [False, True])
 def test_batch_config4_shapes_match_oracle(L, config4, tuned):
-    """The four shapes advance in one persistent launch (graph replay), with
-    the default tiling and with the autotuner's choice.  After one automatic
+    """The four shapes advance together (graph replay), with the default
+    configuration and with the autotuner's choice.  After one automatic
     attempt every pair has the oracle's decision and lambda, its loss within
     2e-7, its field within 1e-4 voxel and the smoothed gradient of its
     accepted field within 2e-5 of max|g|, element by element."""
