@@ -35,8 +35,22 @@ __device__ void decide_block(DevState* st, const double* __restrict__ partials,
     cur_st = *st;
     skip = (mode == 0 && cur_st.stalled) ? 1 : 0;
   }
+  // each thread sums partials t, t + NT, t + 2 NT, ... in that order; the
+  // first kLoads of them are all requested before the first add, so a level
+  // with up to kLoads * NT partials waits for one memory round trip, not one
+  // per NT partials
+  constexpr int kLoads = 8;
+  double v[kLoads];
+#pragma unroll
+  for (int j = 0; j < kLoads; ++j) {
+    const int k = threadIdx.x + j * NT;
+    v[j] = k < nparts ? partials[k] : 0.0;
+  }
   double s = 0.0;
-  for (int k = threadIdx.x; k < nparts; k += NT) s += partials[k];
+#pragma unroll
+  for (int j = 0; j < kLoads; ++j)
+    if (threadIdx.x + j * NT < nparts) s += v[j];
+  for (int k = threadIdx.x + kLoads * NT; k < nparts; k += NT) s += partials[k];
   sh[threadIdx.x] = s;
   __syncthreads();
   if (skip) {
