@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "pyramid.h"
 #include "lmr_internal.h"
 
 using namespace lmr;
@@ -313,10 +314,10 @@ lmr_status lmr_begin(lmr_ctx* c, const void* F, const void* M, const float* fiel
   if (!c || !F || !M || !(lambda0 > 0.0)) return LMR_EINVAL;
   hipStream_t s = c->stream;
   const size_t bytes = sizeof(float) * 3 * c->g.N;
-  if (field)
-    LMR_HIP(hipMemcpyAsync(c->U[0], field, bytes, hipMemcpyDeviceToDevice, s));
-  else
+  if (!field)
     LMR_HIP(launch_fill(c->U[0], 3 * c->g.N, 0.0f, s));
+  else if (field != c->U[0])  // a field already in place is kept as it is
+    LMR_HIP(hipMemcpyAsync(c->U[0], field, bytes, hipMemcpyDeviceToDevice, s));
   const int sim = c->p.similarity;
   if (sim == LMR_SIM_LNCC) {
     LMR_HIP(launch_fstat(F, c->img, c->g, c->p, c->fstat, s));
@@ -690,8 +691,7 @@ struct lmr_pyramid {
   lmr_ctx* lv[8];
   float* Fl[8];   // pooled fixed image (null at factor 1)
   float* Ml[8];   // pooled moving image
-  float* ul[8];   // field handed to level l
-  void* arena;
+  void* arena = nullptr;
   // HIP graphs of the attempt sequences, keyed by (level, images, attempts);
   // captured on a private stream, launched on the pyramid's stream
   bool use_graphs = true;
@@ -805,17 +805,15 @@ lmr_status lmr_pyramid_create(lmr_pyramid** out, int nz, int ny, int nx, lmr_dty
     y->dims[l][1] = ny / f;
     y->dims[l][2] = nx / f;
     const size_t n = (size_t)(nz / f) * (ny / f) * (nx / f);
-    total += align256(4 * 3 * n) + (f > 1 ? 2 * align256(4 * n) : 0);
+    total += f > 1 ? 2 * align256(4 * n) : 0;
   }
-  if (hipMalloc(&y->arena, total) != hipSuccess) {
+  if (total > 0 && hipMalloc(&y->arena, total) != hipSuccess) {
     delete y;
     return LMR_ENOMEM;
   }
   char* q = static_cast<char*>(y->arena);
   for (int l = 0; l < nlevels; ++l) {
     const size_t n = (size_t)y->dims[l][0] * y->dims[l][1] * y->dims[l][2];
-    y->ul[l] = reinterpret_cast<float*>(q);
-    q += align256(4 * 3 * n);
     y->Fl[l] = y->Ml[l] = nullptr;
     if (factors[l] > 1) {
       y->Fl[l] = reinterpret_cast<float*>(q);
@@ -861,11 +859,12 @@ lmr_status lmr_pyramid_run(lmr_pyramid* y, const void* F, const void* M,
     }
     const float* u0 = nullptr;
     if (l > 0) {
-      lmr_status st = lmr_get_field(y->lv[l - 1], y->ul[l - 1]);
-      if (st != LMR_OK) return st;
-      LMR_HIP(launch_upsample_field(y->ul[l - 1], y->dims[l - 1][0], y->dims[l - 1][1],
-                                    y->dims[l - 1][2], y->ul[l], y->stream));
-      u0 = y->ul[l];
+      // the coarse level's current field, upsampled straight into this
+      // level's first field buffer (lmr_begin then copies nothing)
+      const lmr_ctx* pc = y->lv[l - 1];
+      LMR_HIP(launch_upsample_cur(pc->st, pc->U[0], pc->U[1], y->dims[l - 1][0],
+                                  y->dims[l - 1][1], y->dims[l - 1][2], c->U[0], y->stream));
+      u0 = c->U[0];
     }
     lmr_status st = lmr_begin(c, Fl, Ml, u0, lambda0);
     if (st != LMR_OK) return st;
