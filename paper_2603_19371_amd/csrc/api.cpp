@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "pass_decision.h"
 #include "pyramid.h"
 #include "lmr_internal.h"
 
@@ -130,12 +131,26 @@ lmr_status enqueue_attempt(lmr_ctx* c, const void* F, const void* M, int force) 
   else
     LMR_HIP(launch_mse_fwd(F, c->img, c->Mw, c->g, c->nparts, c->partials, nullptr, c->st, s));
   LMR_HIP(mark(LMR_K_FWD, 1));
+  // levels with few partials take the decision in the backward pass, which
+  // stages the decided state; the smoothing pass makes it the pair state
+  const bool dec_in_bwd = sim == LMR_SIM_LNCC && bwd_takes_decision(c->g, c->p, c->nparts);
   LMR_HIP(mark(LMR_K_DECIDE, 0));
-  LMR_HIP(launch_decide(c->st, c->partials, sim == LMR_SIM_MI ? 1 : c->nparts, c->g.N, c->dp,
-                        0, force, 0.0, nullptr, s));
+  if (!dec_in_bwd)
+    LMR_HIP(launch_decide(c->st, c->partials, sim == LMR_SIM_MI ? 1 : c->nparts, c->g.N,
+                          c->dp, 0, force, 0.0, nullptr, s));
   LMR_HIP(mark(LMR_K_DECIDE, 1));
   LMR_HIP(mark(LMR_K_BWD, 0));
-  if (sim == LMR_SIM_LNCC)
+  if (dec_in_bwd) {
+    PassDecision pd{};
+    pd.partials = c->partials;
+    pd.nparts = c->nparts;
+    pd.N = c->g.N;
+    pd.dp = c->dp;
+    pd.force = force;
+    pd.next = c->st_next;
+    LMR_HIP(launch_bwd_decide(F, M, c->img, c->Mw, c->maps, c->g, c->p, c->st, c->U[0],
+                              c->U[1], c->graw, c->graw, pd, s));
+  } else if (sim == LMR_SIM_LNCC)
     LMR_HIP(launch_bwd(F, M, c->img, c->Mw, c->maps, c->g, c->p, c->st, c->U[0], c->U[1],
                        nullptr, c->graw, c->graw, s));
   else if (sim == LMR_SIM_MSE)
@@ -147,7 +162,10 @@ lmr_status enqueue_attempt(lmr_ctx* c, const void* F, const void* M, int force) 
     LMR_HIP(launch_demons_keep(F, c->img, c->Mw, c->graw, c->g, c->st, c->maps, s));
   LMR_HIP(mark(LMR_K_BWD, 1));
   LMR_HIP(mark(LMR_K_SMOOTH, 0));
-  if (sim != LMR_SIM_DEMONS) {
+  if (dec_in_bwd) {
+    LMR_HIP(launch_smooth_commit(c->graw, c->g, c->p, c->st_next, c->st, c->G, s));
+    if (ex.mode == 1) LMR_HIP(launch_tile_hessian(c->G, c->g, c->p.tile, c->H, c->st, 2, s));
+  } else if (sim != LMR_SIM_DEMONS) {
     LMR_HIP(launch_smooth(c->graw, c->g, c->p, c->st, c->G, s));
     // eq. tilen: the pooled matrices of the new gradient (timed with P5)
     if (ex.mode == 1) LMR_HIP(launch_tile_hessian(c->G, c->g, c->p.tile, c->H, c->st, 2, s));
@@ -236,7 +254,7 @@ lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
                           align256(sizeof(float) * 4 * N),
                           align256(sizeof(float) * N),
                           align256(sizeof(double) * c->nparts),
-                          align256(sizeof(DevState)),
+                          align256(2 * sizeof(DevState)),  // the pair state and its staging slot
                           align256(sizeof(double)),
                           align256(sizeof(DevState)),
                           align256(sizeof(double)),
@@ -274,6 +292,7 @@ lmr_status lmr_create(lmr_ctx** out, int nz, int ny, int nx, lmr_dtype img,
   c->Mw = reinterpret_cast<float*>(q); q += sizes[5];
   c->partials = reinterpret_cast<double*>(q); q += sizes[6];
   c->st = reinterpret_cast<DevState*>(q); q += sizes[7];
+  c->st_next = c->st + 1;
   c->probe = reinterpret_cast<double*>(q); q += sizes[8];
   c->st_probe = reinterpret_cast<DevState*>(q); q += sizes[9];
   c->part_probe = reinterpret_cast<double*>(q); q += sizes[10];

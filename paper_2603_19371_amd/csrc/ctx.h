@@ -35,6 +35,7 @@ struct lmr_ctx {
   double* partials;
   int nparts;
   lmr::DevState* st;
+  lmr::DevState* st_next;  // the state a backward pass decided, until P5 stores it in st
   double* probe;
   lmr::DevState* st_probe;
   double* part_probe;

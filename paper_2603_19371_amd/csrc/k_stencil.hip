@@ -4,6 +4,8 @@
 // contiguous range of tiles and shares their halos in its L2.
 #include <algorithm>
 
+#include "decide.h"
+#include "pass_decision.h"
 #include "stencil.h"
 
 namespace lmr {
@@ -32,36 +34,76 @@ struct StencilWaves<BwdPol<uint16_t, double>> {
   static constexpr int value = 4;
 };
 
-// need: 0 always run, 1 skip a frozen pair, 2 run only after an acceptance
-template <int R, int TY, class P>
-__global__ void __launch_bounds__(kTX* TY)
-    __attribute__((amdgpu_waves_per_eu(StencilWaves<P>::value)))
-    k_stencil(const P pol, Geom g, Tiling t, const DevState* st, int need) {
-  if (st && need) {
-    if (st->stalled) return;
-    if (need == 2 && !st->accepted) return;
+// The decision of the attempt inside a pass of NT threads (pass_decision.h):
+// every block reduces the partials and decides on the pair state st; block 0
+// stores the result in pd.next.  Returns the decided state, in LDS.
+template <int NT>
+__device__ const DevState* decide_in_pass(const DevState* st, const PassDecision& pd) {
+  __shared__ double sh[NT];
+  __shared__ DevState s_next;
+  DevState cur;
+  if (threadIdx.x == 0) cur = *st;
+  const double S = reduce_partials<NT>(pd.partials, pd.nparts, sh);
+  if (threadIdx.x == 0) {
+    const DevState n = decide_next(cur, -S / static_cast<double>(pd.N), pd.dp, pd.force);
+    if (blockIdx.x == 0) *pd.next = n;
+    s_next = n;
   }
+  __syncthreads();
+  return &s_next;
+}
+
+// Whether a block of a pass runs, and the state it runs on (rs; null without
+// a pair state).  need: 0 always run, 1 skip a frozen pair, 2 run only after
+// an acceptance.  DEC: the pass takes the decision first and runs on the
+// decided state.  pd.commit: block 0 first stores st there.
+template <int NT, bool DEC>
+__device__ __forceinline__ bool pass_state(const DevState* st, int need,
+                                           const PassDecision& pd, const DevState*& rs) {
+  if constexpr (DEC) {
+    rs = decide_in_pass<NT>(st, pd);
+    return rs->accepted != 0;
+  } else {
+    rs = st;
+    if (pd.commit && blockIdx.x == 0 && threadIdx.x == 0) *pd.commit = *st;
+    if (st && need) {
+      if (st->stalled) return false;
+      if (need == 2 && !st->accepted) return false;
+    }
+    return true;
+  }
+}
+
+// A pass that takes the decision is held to the waves per SIMD the pass has
+// without it (left alone, the compiler gives the decision's registers to the
+// stencil and loses a wave).
+template <int R, int TY, class P, bool DEC>
+__global__ void __launch_bounds__(kTX* TY)
+    __attribute__((amdgpu_waves_per_eu(DEC ? 4 : StencilWaves<P>::value)))
+    k_stencil(const P pol, Geom g, Tiling t, const DevState* st, int need, PassDecision pd) {
+  const DevState* rs;
+  if (!pass_state<kTX * TY, DEC>(st, need, pd, rs)) return;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   int x0, y0, z0;
   tile_origin(t, tile, TY, x0, y0, z0);
-  typename P::Local loc = pol.begin_block(st);
+  typename P::Local loc = pol.begin_block(rs);
   stencil_tile<R, TY>(pol, g, x0, y0, z0, min(z0 + t.cz, g.nz), loc);
   pol.end_tile(loc, tile);  // partials in tile order, as in the batched form
 }
 
 // The same stencil on TZ x kT3 x kT3 bricks (small volumes; stencil.h).
-template <int R, class P, int TZ>
+template <int R, class P, int TZ, bool DEC>
 __global__ void __launch_bounds__(kCubeThreads)
-    k_cube(const P pol, Geom g, int cubes_x, int cubes_y, const DevState* st, int need) {
-  if (st && need) {
-    if (st->stalled) return;
-    if (need == 2 && !st->accepted) return;
-  }
+    __attribute__((amdgpu_waves_per_eu(DEC ? 4 : 1)))
+    k_cube(const P pol, Geom g, int cubes_x, int cubes_y, const DevState* st, int need,
+           PassDecision pd) {
+  const DevState* rs;
+  if (!pass_state<kCubeThreads, DEC>(st, need, pd, rs)) return;
   __shared__ CubeLds<R, P, TZ> sm;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int x0 = (b % cubes_x) * kT3, y0 = ((b / cubes_x) % cubes_y) * kT3;
   const int z0 = (b / (cubes_x * cubes_y)) * TZ;
-  typename P::Local loc = pol.begin_block(st);
+  typename P::Local loc = pol.begin_block(rs);
   stencil_cube<R, TZ>(pol, g, x0, y0, z0, loc, sm);
   pol.end_tile(loc, b);
 }
@@ -130,33 +172,35 @@ int cube_count(const Geom& g) {
   return cube_columns(g) * ((g.nz + tz - 1) / tz);
 }
 
-template <class P, int R>
+template <class P, int R, bool DEC = false>
 hipError_t run(const P& pol, const Geom& g, bool cubes, const DevState* st, int need,
-               hipStream_t s) {
+               hipStream_t s, const PassDecision& pd = PassDecision{}) {
   if (cubes) {
     const int cx = (g.nx + kT3 - 1) / kT3, cy = (g.ny + kT3 - 1) / kT3;
     if (cube_tz(g) == 4)
-      hipLaunchKernelGGL((k_cube<R, P, 4>), dim3(cube_count(g)), dim3(kCubeThreads), 0, s,
-                         pol, g, cx, cy, st, need);
+      hipLaunchKernelGGL((k_cube<R, P, 4, DEC>), dim3(cube_count(g)), dim3(kCubeThreads), 0,
+                         s, pol, g, cx, cy, st, need, pd);
+    else if constexpr (DEC)
+      return hipErrorInvalidValue;  // 8-plane bricks keep the decision kernel
     else
-      hipLaunchKernelGGL((k_cube<R, P, 8>), dim3(cube_count(g)), dim3(kCubeThreads), 0, s,
-                         pol, g, cx, cy, st, need);
+      hipLaunchKernelGGL((k_cube<R, P, 8, false>), dim3(cube_count(g)), dim3(kCubeThreads),
+                         0, s, pol, g, cx, cy, st, need, pd);
     return hipGetLastError();
   }
   const Tiling t = march_tiling(g, R);
-  hipLaunchKernelGGL((k_stencil<R, kTY, P>), dim3(t.tiles()), dim3(kTX * kTY), 0, s, pol,
-                     g, t, st, need);
+  hipLaunchKernelGGL((k_stencil<R, kTY, P, DEC>), dim3(t.tiles()), dim3(kTX * kTY), 0, s,
+                     pol, g, t, st, need, pd);
   return hipGetLastError();
 }
 
-template <class P>
+template <class P, bool DEC = false>
 hipError_t run_box(const P& pol, int window, const Geom& g, bool cubes, const DevState* st,
-                   int need, hipStream_t s) {
+                   int need, hipStream_t s, const PassDecision& pd = PassDecision{}) {
   switch (window / 2) {
-    case 1: return run<P, 1>(pol, g, cubes, st, need, s);
-    case 2: return run<P, 2>(pol, g, cubes, st, need, s);
-    case 3: return run<P, 3>(pol, g, cubes, st, need, s);
-    case 4: return run<P, 4>(pol, g, cubes, st, need, s);
+    case 1: return run<P, 1, DEC>(pol, g, cubes, st, need, s, pd);
+    case 2: return run<P, 2, DEC>(pol, g, cubes, st, need, s, pd);
+    case 3: return run<P, 3, DEC>(pol, g, cubes, st, need, s, pd);
+    case 4: return run<P, 4, DEC>(pol, g, cubes, st, need, s, pd);
     default: return hipErrorInvalidValue;
   }
 }
@@ -194,7 +238,7 @@ template <typename T, typename Acc>
 hipError_t bwd_t(const T* F, const T* M, const float* Mw, const float* maps,
                  const Geom& g, const lmr_params& p, const DevState* st,
                  const float* U0, const float* U1, const float* ue, const float* dMw,
-                 float* graw, hipStream_t s) {
+                 float* graw, hipStream_t s, const PassDecision* pd = nullptr) {
   BwdPol<T, Acc> pol;
   pol.F = F;
   pol.M = M;
@@ -207,18 +251,21 @@ hipError_t bwd_t(const T* F, const T* M, const float* Mw, const float* maps,
   pol.graw = graw;
   pol.g = g;
   pol.inv_n = 1.0 / ((double)p.window * p.window * p.window);
+  if (pd) return run_box<BwdPol<T, Acc>, true>(pol, p.window, g, use_cubes(g, p), st, 2, s, *pd);
   return run_box(pol, p.window, g, use_cubes(g, p), st, 2, s);
 }
 
 template <int R>
 hipError_t smooth_r(const float* in, float* out, const Geom& g, const lmr_params& p,
-                    const DevState* st, hipStream_t s) {
+                    const DevState* st, hipStream_t s, DevState* commit = nullptr) {
   SmoothPol<R> pol;
   pol.in = in;
   pol.out = out;
   pol.N = static_cast<int>(g.N);
   gauss_taps<R>(p.grad_sigma, pol.w);
-  return run<SmoothPol<R>, R>(pol, g, use_cubes(g, p), st, 2, s);
+  PassDecision pd{};
+  pd.commit = commit;
+  return run<SmoothPol<R>, R>(pol, g, use_cubes(g, p), st, 2, s, pd);
 }
 
 }  // namespace
@@ -296,6 +343,48 @@ hipError_t launch_smooth(const float* graw, const Geom& g, const lmr_params& p,
     case 4: return smooth_r<4>(graw, out, g, p, st, s);
     case 5: return smooth_r<5>(graw, out, g, p, st, s);
     case 6: return smooth_r<6>(graw, out, g, p, st, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool bwd_takes_decision(const Geom& g, const lmr_params& p, int nparts) {
+  return nparts <= kPassDecisionMaxParts && !(use_cubes(g, p) && cube_tz(g) == 8);
+}
+
+hipError_t launch_bwd_decide(const void* F, const void* M, lmr_dtype t, const float* Mw,
+                             const float* maps, const Geom& g, const lmr_params& p,
+                             const DevState* st, const float* U0, const float* U1,
+                             const float* dMw, float* graw, const PassDecision& pd,
+                             hipStream_t s) {
+  if (!st || !pd.partials || !pd.next || !bwd_takes_decision(g, p, pd.nparts))
+    return hipErrorInvalidValue;
+  if (t == LMR_BF16) {
+    const uint16_t *f = static_cast<const uint16_t*>(F), *m = static_cast<const uint16_t*>(M);
+    return p.accum == LMR_ACC_F32C
+               ? bwd_t<uint16_t, F32C>(f, m, Mw, maps, g, p, st, U0, U1, nullptr, dMw, graw,
+                                       s, &pd)
+               : bwd_t<uint16_t, double>(f, m, Mw, maps, g, p, st, U0, U1, nullptr, dMw, graw,
+                                         s, &pd);
+  }
+  const float *f = static_cast<const float*>(F), *m = static_cast<const float*>(M);
+  return p.accum == LMR_ACC_F32C
+             ? bwd_t<float, F32C>(f, m, Mw, maps, g, p, st, U0, U1, nullptr, dMw, graw, s, &pd)
+             : bwd_t<float, double>(f, m, Mw, maps, g, p, st, U0, U1, nullptr, dMw, graw, s,
+                                    &pd);
+}
+
+hipError_t launch_smooth_commit(const float* graw, const Geom& g, const lmr_params& p,
+                                const DevState* next, DevState* st, float* out,
+                                hipStream_t s) {
+  if (!next || !st) return hipErrorInvalidValue;
+  switch (gauss_radius(p.grad_sigma)) {
+    case 0: return smooth_r<0>(graw, out, g, p, next, s, st);
+    case 1: return smooth_r<1>(graw, out, g, p, next, s, st);
+    case 2: return smooth_r<2>(graw, out, g, p, next, s, st);
+    case 3: return smooth_r<3>(graw, out, g, p, next, s, st);
+    case 4: return smooth_r<4>(graw, out, g, p, next, s, st);
+    case 5: return smooth_r<5>(graw, out, g, p, next, s, st);
+    case 6: return smooth_r<6>(graw, out, g, p, next, s, st);
     default: return hipErrorInvalidValue;
   }
 }
