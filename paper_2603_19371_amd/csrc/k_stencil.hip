@@ -74,12 +74,19 @@ __device__ __forceinline__ bool pass_state(const DevState* st, int need,
   }
 }
 
-// A pass that takes the decision is held to the waves per SIMD the pass has
-// without it (left alone, the compiler gives the decision's registers to the
-// stencil and loses a wave).
+// A marching pass that takes the decision is held to the waves per SIMD the
+// pass has without it (left alone, the compiler gives the decision's registers
+// to the stencil and loses a wave): four with FP64 sums, three with
+// compensated FP32 sums (which spill at four).
+template <class P>
+struct DecidingWaves {
+  static constexpr int value = std::is_same<typename P::Acc, F32C>::value ? 3 : 4;
+};
+
 template <int R, int TY, class P, bool DEC>
 __global__ void __launch_bounds__(kTX* TY)
-    __attribute__((amdgpu_waves_per_eu(DEC ? 4 : StencilWaves<P>::value)))
+    __attribute__((amdgpu_waves_per_eu(DEC ? DecidingWaves<P>::value
+                                           : StencilWaves<P>::value)))
     k_stencil(const P pol, Geom g, Tiling t, const DevState* st, int need, PassDecision pd) {
   const DevState* rs;
   if (!pass_state<kTX * TY, DEC>(st, need, pd, rs)) return;
@@ -175,22 +182,26 @@ int cube_count(const Geom& g) {
 template <class P, int R, bool DEC = false>
 hipError_t run(const P& pol, const Geom& g, bool cubes, const DevState* st, int need,
                hipStream_t s, const PassDecision& pd = PassDecision{}) {
-  if (cubes) {
-    const int cx = (g.nx + kT3 - 1) / kT3, cy = (g.ny + kT3 - 1) / kT3;
-    if (cube_tz(g) == 4)
-      hipLaunchKernelGGL((k_cube<R, P, 4, DEC>), dim3(cube_count(g)), dim3(kCubeThreads), 0,
-                         s, pol, g, cx, cy, st, need, pd);
-    else if constexpr (DEC)
-      return hipErrorInvalidValue;  // 8-plane bricks keep the decision kernel
-    else
-      hipLaunchKernelGGL((k_cube<R, P, 8, false>), dim3(cube_count(g)), dim3(kCubeThreads),
-                         0, s, pol, g, cx, cy, st, need, pd);
+  if constexpr (DEC && R > kPassDecisionMaxRadius) {
+    return hipErrorInvalidValue;  // wider windows keep the decision kernel
+  } else {
+    if (cubes) {
+      const int cx = (g.nx + kT3 - 1) / kT3, cy = (g.ny + kT3 - 1) / kT3;
+      if (cube_tz(g) == 4)
+        hipLaunchKernelGGL((k_cube<R, P, 4, DEC>), dim3(cube_count(g)), dim3(kCubeThreads),
+                           0, s, pol, g, cx, cy, st, need, pd);
+      else if constexpr (DEC)
+        return hipErrorInvalidValue;  // 8-plane bricks keep the decision kernel
+      else
+        hipLaunchKernelGGL((k_cube<R, P, 8, false>), dim3(cube_count(g)),
+                           dim3(kCubeThreads), 0, s, pol, g, cx, cy, st, need, pd);
+      return hipGetLastError();
+    }
+    const Tiling t = march_tiling(g, R);
+    hipLaunchKernelGGL((k_stencil<R, kTY, P, DEC>), dim3(t.tiles()), dim3(kTX * kTY), 0, s,
+                       pol, g, t, st, need, pd);
     return hipGetLastError();
   }
-  const Tiling t = march_tiling(g, R);
-  hipLaunchKernelGGL((k_stencil<R, kTY, P, DEC>), dim3(t.tiles()), dim3(kTX * kTY), 0, s,
-                     pol, g, t, st, need, pd);
-  return hipGetLastError();
 }
 
 template <class P, bool DEC = false>
@@ -348,7 +359,8 @@ hipError_t launch_smooth(const float* graw, const Geom& g, const lmr_params& p,
 }
 
 bool bwd_takes_decision(const Geom& g, const lmr_params& p, int nparts) {
-  return nparts <= kPassDecisionMaxParts && !(use_cubes(g, p) && cube_tz(g) == 8);
+  return nparts <= kPassDecisionMaxParts && p.window / 2 <= kPassDecisionMaxRadius &&
+         !(use_cubes(g, p) && cube_tz(g) == 8);
 }
 
 hipError_t launch_bwd_decide(const void* F, const void* M, lmr_dtype t, const float* Mw,

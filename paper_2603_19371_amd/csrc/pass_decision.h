@@ -15,6 +15,9 @@ namespace lmr {
 // Levels with at most this many partials take the decision in the backward
 // pass; above it each block's reduction costs more than the launch it saves.
 constexpr int kPassDecisionMaxParts = 1024;
+// Box windows up to 2 * 3 + 1 = 7: with a wider window the deciding pass would
+// spill registers at the occupancy of the pass without the decision.
+constexpr int kPassDecisionMaxRadius = 3;
 
 struct PassDecision {
   const double* partials;  // the forward pass's partials (null: no decision)
@@ -27,8 +30,8 @@ struct PassDecision {
 };
 
 // Whether the backward pass of this level takes the decision: at most
-// kPassDecisionMaxParts partials, on the march or on 4-plane bricks (the
-// 8-plane brick pass would spill registers with it).
+// kPassDecisionMaxParts partials, a window of at most 7, on the march or on
+// 4-plane bricks (the 8-plane brick pass would spill registers with it).
 bool bwd_takes_decision(const Geom& g, const lmr_params& p, int nparts);
 // P4 with the decision: st is the pair state before the attempt (read only).
 hipError_t launch_bwd_decide(const void* F, const void* M, lmr_dtype t, const float* Mw,
