@@ -315,8 +315,9 @@ typedef enum {
   LMR_K_UPDATE = 0,  /* closed form + compositive integration + candidate warp */
   LMR_K_FWD = 1,     /* LNCC forward (box sums, cc, adjoint maps, partials) */
   LMR_K_DECIDE = 2,  /* FP64 loss reduction and decision (LNCC levels with at most
-                        1024 partials, marching or on 4-plane bricks, take it inside
-                        the backward pass: this interval is then its event alone) */
+                        1024 partials and a window of at most 7, marching or on
+                        4-plane bricks, take it inside the backward pass: this
+                        interval is then its event alone) */
   LMR_K_BWD = 3,     /* LNCC backward and warp backward */
   LMR_K_SMOOTH = 4,  /* Gaussian smoothing of the gradient */
   LMR_NUM_KERNELS = 5
